@@ -72,23 +72,32 @@ int orc_locate(const orc_grid *g, const double r[3], const double k[3], orc_cell
         cartesian_bounds(g, c);
         return 1;
     }
-    /* octree: descend from the root through the child holding r */
+    /* octree: descend from the root through the child holding r; faces and
+     * midpoints are lattice points X(I) = box_min + I * (side / 2^40) */
+    const double unit = (g->box_max[0] - g->box_min[0]) / (double)((int64_t)1 << ORC_OCT_DEPTH);
     int64_t node = 0;
-    double lo[3] = { g->box_min[0], g->box_min[1], g->box_min[2] };
-    double size = g->box_max[0] - g->box_min[0];
+    int64_t I[3] = { 0, 0, 0 };
+    int64_t S = (int64_t)1 << ORC_OCT_DEPTH;
     while (g->child[node] >= 0) {
-        double half = 0.5 * size;
+        int64_t half = S / 2;
         int oct = 0;
         for (int d = 0; d < 3; ++d) {
-            int b = side_of(r[d], lo[d] + half, k[d]);
-            if (b) lo[d] += half;
+            double mid = g->box_min[d] + (double)(I[d] + half) * unit;
+            int b = side_of(r[d], mid, k[d]);
+            if (b) I[d] += half;
             oct |= b << d;
         }
         node = g->child[node] + oct;
-        size = half;
+        S = half;
     }
     c->id = node;
-    for (int d = 0; d < 3; ++d) { c->lo[d] = lo[d]; c->hi[d] = lo[d] + size; c->ijk[d] = 0; }
+    c->S = S;
+    for (int d = 0; d < 3; ++d) {
+        c->I[d] = I[d];
+        c->lo[d] = g->box_min[d] + (double)I[d] * unit;
+        c->hi[d] = g->box_min[d] + (double)(I[d] + S) * unit;
+        c->ijk[d] = 0;
+    }
     return 1;
 }
 

@@ -21,8 +21,14 @@ void   orc_perp_basis(const double k[3], double e1[3], double e2[3]);
 typedef struct {
     int64_t id;          /* flat Cartesian index or octree node index */
     int32_t ijk[3];      /* Cartesian indices                          */
+    int64_t I[3], S;     /* octree: lower corner and size on the lattice of
+                            2^ORC_OCT_DEPTH steps per root side          */
     double lo[3], hi[3]; /* cell bounds in cm                          */
 } orc_cell;
+
+/* Octree faces are evaluated as one function of an integer lattice
+ * coordinate, so neighbouring cells see bit-identical shared faces. */
+#define ORC_OCT_DEPTH 40
 
 /* Geometry helpers (oracle_grid.c). */
 int    orc_locate(const orc_grid *g, const double r[3], const double k[3], orc_cell *c);
