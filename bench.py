@@ -1,0 +1,176 @@
+"""Throughput benchmark of the Lyman-alpha transport hot path on one MI355X.
+
+Workload (one step): the dusty uniform sphere -- 64^3 Cartesian grid, line-
+centre radial optical depth tau0 = 1e7 at T = 1e4 K, grey dust tau_d = 1 with
+albedo 0.32, global core-skipping from a*tau0 = 4702, anisotropic scattering,
+500-bin escape spectrum, 1e6 photons from a central point source.  Each step
+transports one full job (fresh seed) with the gas already resident in HBM and
+reads its tallies back.  The headline value is in FP32-bulk mode (FP32
+Voigt/sampling/directions, FP64 position, optical depth and tallies); the same
+steps in all-FP64 mode are reported beside it.
+
+Prints one JSON line.  Only one GPU is supported.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Lyα scatterings/sec on 1 MI355X (mixed vs FP64 plain); p50/p99 job latency"
+VALU_PEAK = 256 * 4 * 16 * 2.4e9      # lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz
+
+# Algorithmic VALU lane-op cost per counted event of the method (FP32-bulk
+# arithmetic; transcendentals and 32-bit integer multiplies at quarter rate).
+# The derivation is written out in the design notes.
+OPS_FP32 = {"uniform": 33, "scat_hi": 400, "upar_tries": 24, "crossings": 65,
+            "peels": 40, "peel_crossings": 60, "scat_dust": 120, "emitted": 200}
+# uniforms per event: 3 per u_par candidate; u_perp (2), mu, phi and tau per
+# H I scattering; albedo, mu, phi, tau per dust scattering; mu, phi, tau per
+# emission; one channel draw per interaction in dusty cells
+DRAWS_PER = {"upar_tries": 3, "scat_hi": 5, "scat_dust": 4, "emitted": 3}
+
+
+def algorithmic_ops(c, dusty=True):
+    draws = sum(DRAWS_PER[k] * c[k] for k in DRAWS_PER)
+    if dusty:
+        draws += c["scat_hi"] + c["scat_dust"] + c["absorbed"]
+    ops = OPS_FP32["uniform"] * draws
+    for k in ("scat_hi", "upar_tries", "crossings", "peels", "peel_crossings", "scat_dust",
+              "emitted"):
+        ops += OPS_FP32[k] * c[k]
+    return ops
+
+
+def workload(n_photons, seed):
+    from paper_1409_4480_amd import inputs
+    return inputs.dusty_sphere(n=64, tau0=1.0e7, n_photons=n_photons, seed=seed)
+
+
+def cpu_baseline(n_photons_full, budget_s=15.0):
+    """The CPU oracle on a bounded sample of the same workload: the first
+    photons of a job, sized to about `budget_s` seconds after a calibration."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    wl = workload(n_photons_full, 1409448002)
+    n_cal = 2000
+    t = time.perf_counter()
+    r = oracle.run(wl["grid"], wl["source"], wl["params"], id_begin=0, id_end=n_cal,
+                   threads=threads)
+    dt = time.perf_counter() - t
+    n = int(min(n_photons_full, max(n_cal, n_cal * budget_s / max(dt, 1e-3))))
+    t = time.perf_counter()
+    r = oracle.run(wl["grid"], wl["source"], wl["params"], id_begin=0, id_end=n,
+                   threads=threads)
+    dt = time.perf_counter() - t
+    scat = r["counters"]["scat_hi"]
+    return {"value": scat / dt, "unit": "scatterings/s", "cores": threads, "kind": "oracle",
+            "sample": f"photons 0..{n - 1} of the 1e6-photon job ({scat} scatterings, "
+                      f"{dt:.1f} s, FP64 scalar C)",
+            "photons_per_s": n / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--photons", type=int, default=1_000_000)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the transport "
+              "shards by photon ranges across GPUs, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1409_4480_amd import colt
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    wl = workload(args.photons, 1409448002)
+    t0 = time.perf_counter()
+    grid = colt.Grid(wl["grid"])
+    torch.cuda.synchronize()
+    grid_setup_ms = (time.perf_counter() - t0) * 1e3
+
+    def run_steps(precision, n_steps, seed0):
+        jobs = [colt.Job(grid, wl["source"], dict(wl["params"], seed=seed0 + i),
+                         precision=precision) for i in range(n_steps)]
+        torch.cuda.synchronize()
+        lat, kern, counters = [], [], []
+        t_start = time.perf_counter()
+        for j in jobs:
+            ts = time.perf_counter()
+            colt.transport([j], block=args.block, blocks_per_cu=args.blocks_per_cu,
+                           time_kernel=True)
+            out = j.tally(wait=True)
+            lat.append((time.perf_counter() - ts) * 1e3)
+            kern.append(colt.last_kernel_ms())
+            counters.append(out["counters"])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        for j in jobs:
+            j.release()
+        return elapsed, lat, kern, counters
+
+    # warm-up, then the timed steps (FP32-bulk headline)
+    if args.warmup:
+        run_steps(colt.FP32_BULK, args.warmup, 7000)
+    el, lat, kern, cnt = run_steps(colt.FP32_BULK, args.steps, 1409448002)
+    scat = sum(c["scat_hi"] for c in cnt)
+    photons = sum(c["emitted"] for c in cnt)
+    value = scat / el
+    kern_avg_ms = float(np.mean(kern))
+    ops = np.mean([algorithmic_ops(c) for c in cnt])
+    achieved = ops / (kern_avg_ms * 1e-3)
+    result = {
+        "metric": METRIC, "value": value, "unit": "scatterings/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "dusty_sphere_64cube_tau1e7", "grid": "64^3 Cartesian",
+                   "tau0": 1.0e7, "T_K": 1.0e4, "tau_dust": 1.0, "albedo": 0.32,
+                   "core_skip": "global x_crit(a tau0=4702)=3.35", "photons_per_step": args.photons,
+                   "spectrum_bins": 500, "precision": "FP32-bulk"},
+        "photons_per_s": photons / el,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "per_step": {"scatterings": scat / args.steps,
+                     "escaped_fraction": sum(c["escaped"] for c in cnt) / photons,
+                     "upar_tries_per_scattering": sum(c["upar_tries"] for c in cnt) / max(scat, 1),
+                     "crossings": sum(c["crossings"] for c in cnt) / args.steps},
+        "grid_setup_ms": grid_setup_ms,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                     "kernel": "k_transport<float>", "kernel_ms": kern_avg_ms,
+                     "ops_per_launch": ops},
+    }
+    if not args.no_fp64:
+        el64, lat64, kern64, cnt64 = run_steps(colt.FP64, args.steps, 1409448002)
+        scat64 = sum(c["scat_hi"] for c in cnt64)
+        result["fp64_plain"] = {
+            "value": scat64 / el64, "unit": "scatterings/s",
+            "ms_per_step": el64 / args.steps * 1e3, "kernel_ms": float(np.mean(kern64)),
+            "latency_ms": {"p50": float(np.percentile(lat64, 50)),
+                           "p99": float(np.percentile(lat64, 99))},
+            "escaped_fraction": sum(c["escaped"] for c in cnt64) /
+            sum(c["emitted"] for c in cnt64)}
+        result["speedup_mixed_vs_fp64"] = value / (scat64 / el64)
+    grid.release()
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(args.photons)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,238 @@
+/*
+ * colt.h -- C ABI of the MI355X Monte-Carlo Lyman-alpha transport library.
+ *
+ * The library transports photon packets through neutral hydrogen (and grey
+ * dust) on Cartesian or octree grids, following the method of Smith,
+ * Safranek-Shrader, Bromm & Milosavljevic (2014, arXiv:1409.4480):
+ *   - optical-depth draws tau = -ln R against the Voigt profile (Sec. 3.1.2,
+ *     eq. lnR) with H(a,x) from the appendix approximation (eq. AB);
+ *   - cell-by-cell ray tracing with the bulk-velocity / temperature frequency
+ *     transform between cells (Sec. 3.1.2);
+ *   - scattering with the atom-velocity draw (parallel component by rejection,
+ *     Sec. 3.2.3; perpendicular components Gaussian, Sec. 3.1.3), the phase
+ *     function (eq. phaseW) and frequency redistribution with recoil (eq. x_f);
+ *   - optional core-skipping (Sec. 3.2.4, eq. xcrit, eq. atau0min);
+ *   - next-event (peel-off) tallies into camera spectra and images (Sec. 6.1,
+ *     eq. SB), and the angle-averaged escape spectrum (Sec. 4).
+ * Grey dust competes with H I at each interaction point; it is not part of the
+ * paper's method and is an extension of this library.
+ *
+ * Conventions
+ *   - Units: cm, cm^-3, K, km/s.  Frequencies are x = (nu - nu0)/Delta nu_D;
+ *     spectra are binned in the lab-frame x measured in Doppler widths at
+ *     T_ref = 1e4 K (v_th,ref = 12.85 km/s), positive towards the blue.
+ *   - Every call returns a colt_status (0 = COLT_OK, < 0 = error); the message
+ *     of the last error on the calling thread is colt_last_error().  No C++
+ *     exception crosses this interface.
+ *   - Descriptor and array arguments are HOST pointers, borrowed for the call
+ *     only; data is copied to the device.  Handles are owned by the library
+ *     until released.  Output buffers of colt_tally are owned by the caller.
+ *   - Device memory comes from the supplied allocator (NULL = hipMalloc).
+ *   - `stream` is a hipStream_t (NULL = default stream).  Calls are
+ *     asynchronous on it unless stated otherwise.
+ *   - Random numbers: photon i of a job draws uniform number k from
+ *     Philox4x32-10 (Salmon et al. 2011) with key = job seed (64 bit) and
+ *     counter = (block lo, block hi, i lo, i hi), one draw order per photon;
+ *     results do not depend on launch shape or job batching.
+ */
+#ifndef COLT_H
+#define COLT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t colt_status;
+#define COLT_OK          0
+#define COLT_ERR_ARG    -1   /* invalid argument or descriptor                  */
+#define COLT_ERR_NOMEM  -2   /* device allocation failed or budget exceeded     */
+#define COLT_ERR_HIP    -3   /* a HIP runtime call failed                       */
+#define COLT_ERR_STATE  -4   /* call not valid in the object's current state    */
+#define COLT_ERR_BUSY   -5   /* work still in flight                            */
+
+#define COLT_N_COUNTERS 16
+/* counter slots of colt_tally_out.counters */
+#define COLT_C_EMITTED        0
+#define COLT_C_ESCAPED        1
+#define COLT_C_ABSORBED       2
+#define COLT_C_SCAT_HI        3   /* executed H I scatterings (core-skipped ones are not events) */
+#define COLT_C_SCAT_DUST      4
+#define COLT_C_CROSSINGS      5   /* cell crossings of the transport march           */
+#define COLT_C_PEELS          6   /* next-event evaluations (event x camera)          */
+#define COLT_C_UPAR_TRIES     7   /* candidate draws of the u_par rejection sampler   */
+#define COLT_C_PEEL_CROSSINGS 8   /* cell crossings of next-event marches             */
+#define COLT_C_CAPPED         9   /* photons stopped by the per-photon event cap      */
+
+typedef struct colt_grid_s *colt_grid;
+typedef struct colt_job_s *colt_job;
+
+/* Device allocator (e.g. a framework's caching allocator).  alloc returns a
+ * device pointer of at least `bytes` bytes, 256-byte aligned, or NULL. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} colt_allocator;
+
+/* Gas on a grid of cells of uniform density, temperature and bulk velocity
+ * (Sec. 3, introduction: initial conditions of v, n, T for each cell of a 3-D
+ * grid with adaptive refinement).
+ * kind 0 (Cartesian): nx*ny*nz cells, index (k*ny + j)*nx + i, x fastest.
+ *   Cells must be cubes: (box_max-box_min)/n equal on all axes.
+ * kind 1 (octree): n_cells nodes; node 0 is the root spanning the (cubic)
+ *   box; child[i] is the index of the first of node i's eight children, or -1
+ *   for a leaf; child c + o holds octant o = ox + 2 oy + 4 oz.  Field arrays
+ *   have one entry per node; entries of internal nodes are ignored.
+ * Photons escape at the box faces, or at the sphere of radius escape_radius
+ * about the box centre when escape_radius > 0. */
+typedef struct {
+    int32_t kind;
+    int32_t nx, ny, nz;
+    double box_min[3], box_max[3];        /* cm                                   */
+    int64_t n_cells;                      /* Cartesian: nx*ny*nz; octree: nodes   */
+    const int32_t *child;                 /* octree only                          */
+    const double *n_HI;                   /* cm^-3                                */
+    const double *T;                      /* K, > 0                               */
+    const double *v;                      /* km/s, 3 per cell interleaved; NULL=0 */
+    const double *k_dust;                 /* cm^-1 grey extinction; NULL = none   */
+    const double *atau_nl;                /* non-local a*tau per cell; NULL = 0   */
+    double dust_albedo;                   /* scattering probability per dust event */
+    double escape_radius;                 /* cm; 0 = box faces                    */
+} colt_grid_desc;
+
+/* Photon sources (Sec. 3.1.1).  kind 0: point at pos[0]; kind 1: Gaussian
+ * blob of width sigma about pos[0]; kind 2: n_src points chosen with
+ * probability proportional to weight (NULL = equal).  freq_mode 0 emits at
+ * comoving line centre x = 0; freq_mode 1 draws x = x_nat + k.u_atom with a
+ * Lorentzian x_nat and a thermal atom velocity (eq. init_freq). */
+typedef struct {
+    int32_t kind;
+    int32_t n_src;
+    const double *pos;                    /* 3*n_src, cm                          */
+    const double *weight;                 /* n_src or NULL                        */
+    double sigma;                         /* cm (kind 1)                          */
+    int32_t freq_mode;
+} colt_source_desc;
+
+#define COLT_FP64      0   /* all arithmetic in double precision                */
+#define COLT_FP32_BULK 1   /* Voigt, sampling, directions in float; position,   */
+                           /* optical depth and tallies in double              */
+
+typedef struct {
+    uint64_t n_photons;
+    uint64_t seed;
+    int32_t precision;                    /* COLT_FP64 or COLT_FP32_BULK          */
+    int32_t xcrit_mode;                   /* 0 off; 1 global: x_crit(atau0);      */
+                                          /* 2 local: a tau_cell + atau_nl[cell]  */
+    double atau0;                         /* a*tau0 for xcrit_mode 1              */
+    int32_t recoil;                       /* recoil term g(mu - 1) of eq. x_f     */
+    int32_t isotropic;                    /* 1: isotropic H I scattering          */
+    int32_t n_bins;                       /* escape spectrum bins over [x_min,x_max) */
+    double x_min, x_max;
+    int32_t n_cams;                       /* next-event observers (<= 64)         */
+    const double *cam_dir;                /* 3*n_cams unit vectors (host)         */
+    int32_t cam_nbins;
+    double cam_xmin, cam_xmax;
+    int32_t cam_npix;                     /* images of cam_npix^2 pixels          */
+    double cam_fov;                       /* cm, image side about the box centre  */
+    double tau_peel_max;                  /* next-event cut-off (paper: 50)       */
+    int32_t record;                       /* 1: keep per-photon records           */
+    uint64_t max_events;                  /* per-photon event cap; 0 = 2^62       */
+} colt_job_params;
+
+/* Launch shape of colt_transport; NULL or zero fields take defaults. */
+typedef struct {
+    int32_t block;                        /* threads per workgroup (64..1024)     */
+    int32_t blocks_per_cu;                /* resident workgroups per CU (grid size) */
+    uint64_t photons_per_job;             /* photons taken from each job per call; */
+                                          /* 0 = all that remain                   */
+    int32_t time_kernel;                  /* 1: time the transport kernel with    */
+                                          /* events (see colt_last_kernel_ms)      */
+} colt_launch;
+
+typedef struct {
+    double *spectrum;     /* n_bins + 2 photon counts: [0] below x_min,           */
+                          /* [1..n_bins] bins, [n_bins+1] at or above x_max       */
+    double *cam_spec;     /* n_cams * cam_nbins, sum of W exp(-tau)                */
+    double *cam_img;      /* n_cams * npix * npix, row v, column u                 */
+    uint64_t counters[COLT_N_COUNTERS];
+    /* per-photon records (job created with record = 1; NULL skips a field)    */
+    double *rec_x;        /* n_photons, final lab-frame x                          */
+    int32_t *rec_nscat;   /* n_photons, H I scatterings                            */
+    int32_t *rec_status;  /* n_photons, 1 escaped, 2 absorbed, 3 capped            */
+    double *rec_pos;      /* 3*n_photons, final position (cm)                      */
+    double *rec_peel;     /* n_photons*n_cams, summed W exp(-tau) per camera        */
+} colt_tally_out;
+
+/* Copies the gas of `desc` to the device and derives per-cell line
+ * quantities (Sec. 2: v_th, a, sigma_0; Sec. 3.2.2: x_cw; eq. recoil_parameter)
+ * with a device kernel on `stream`.  The descriptor arrays may be reused on
+ * return.  Errors: COLT_ERR_ARG (bad shape, non-cubic cells, malformed
+ * octree), COLT_ERR_NOMEM, COLT_ERR_HIP. */
+colt_status colt_init_grid(const colt_grid_desc *desc, const colt_allocator *alloc,
+                           void *stream, colt_grid *out);
+
+/* Registers a transfer job on a grid: sources, photon count, physics options
+ * and tally layout.  Allocates and zeroes the job's device tallies on the
+ * grid's stream.  The job keeps a reference to the grid.
+ * Errors: COLT_ERR_ARG, COLT_ERR_NOMEM, COLT_ERR_HIP. */
+colt_status colt_emit(colt_grid grid, const colt_source_desc *src,
+                      const colt_job_params *params, colt_job *out);
+
+/* Transports photons of n_jobs jobs in one persistent launch per precision
+ * mode on `stream` (asynchronous).  Each job contributes its next
+ * `photons_per_job` photons (all remaining if 0); lanes that finish a photon
+ * take the next one from a shared queue, so jobs of uneven cost share the
+ * device.  Errors: COLT_ERR_ARG, COLT_ERR_STATE (a job already complete),
+ * COLT_ERR_HIP. */
+colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
+                           void *stream);
+
+/* Copies a job's tallies to caller buffers (sizes from its params).  With
+ * wait = 1 it first synchronises the job's last stream; with wait = 0 it
+ * returns COLT_ERR_BUSY if work is still in flight. */
+colt_status colt_tally(colt_job job, colt_tally_out *out, int32_t wait);
+
+/* Photons handed to transport so far and the job's total. */
+colt_status colt_job_status(colt_job job, uint64_t *launched, uint64_t *total);
+
+/* Device bytes held by a grid or a job (for admission control). */
+size_t colt_grid_bytes(colt_grid grid);
+size_t colt_job_bytes(colt_job job);
+
+/* Duration in ms of the last transport kernel launched with time_kernel = 1
+ * on the calling thread (synchronises on its end event); < 0 if none. */
+double colt_last_kernel_ms(void);
+
+void colt_release_job(colt_job job);
+/* COLT_ERR_STATE if jobs still reference the grid. */
+colt_status colt_release_grid(colt_grid grid);
+const char *colt_last_error(void);
+
+/* ---- device checks of the building blocks (host arrays in and out) ---- */
+
+/* Per-cell derived fields as computed on the device, 10 doubles per cell:
+ * k0 (cm^-1), a, v_th (km/s), u_x, u_y, u_z (bulk velocity / v_th),
+ * k_dust (cm^-1), x_cw, g, atau_nl. */
+colt_status colt_grid_fields(colt_grid grid, double *out);
+
+/* H(a, x) (eq. AB) evaluated on the device in the given precision. */
+colt_status colt_eval_voigt(int32_t precision, const double *a, const double *x, int64_t n,
+                            double *out, void *stream);
+
+/* Draws n samples of one sampler on the device; sample i uses photon stream
+ * (seed, i) from its first draw, exactly as in transport.
+ *   what 0: u_par for (a = p0, x = p1, x_cw = p2)   out[n], draws[n] uniforms used
+ *   what 1: u_perp pair with cut-off p0              out[2n]
+ *   what 2: mu for W ~ 1 + p0 mu^2                    out[n]
+ *   what 3: uniform numbers (k = 0 .. p0-1 of stream i) out[n*p0] */
+colt_status colt_sample(int32_t what, int32_t precision, double p0, double p1, double p2,
+                        uint64_t seed, int64_t n, double *out, int32_t *draws, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COLT_H */

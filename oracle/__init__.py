@@ -18,7 +18,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 
 N_COUNTERS = 16
 COUNTER_NAMES = ["emitted", "escaped", "absorbed", "scat_hi", "scat_dust", "crossings",
-                 "peels", "upar_tries", "peel_crossings"]
+                 "peels", "upar_tries", "peel_crossings", "capped"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -47,7 +47,8 @@ class _Params(ctypes.Structure):
                 ("x_max", ctypes.c_double), ("n_cams", ctypes.c_int32), ("cam_dir", _dp),
                 ("cam_nbins", ctypes.c_int32), ("cam_xmin", ctypes.c_double),
                 ("cam_xmax", ctypes.c_double), ("cam_npix", ctypes.c_int32),
-                ("cam_fov", ctypes.c_double), ("tau_peel_max", ctypes.c_double)]
+                ("cam_fov", ctypes.c_double), ("tau_peel_max", ctypes.c_double),
+                ("max_events", ctypes.c_uint64)]
 
 
 class _Out(ctypes.Structure):
@@ -238,6 +239,7 @@ def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=No
     p.cam_npix = int(params.get("cam_npix", 0))
     p.cam_fov = float(params.get("cam_fov", 1.0))
     p.tau_peel_max = float(params.get("tau_peel_max", 50.0))
+    p.max_events = int(params.get("max_events", 0))
 
     o = _Out()
     spectrum = np.zeros(p.n_bins + 2)

@@ -71,11 +71,14 @@ typedef struct {
     int32_t cam_npix;          /* square images of cam_npix^2 pixels                   */
     double cam_fov;            /* cm, image side, centred on the box centre           */
     double tau_peel_max;       /* next-event march cut-off (Sec. 6.1 uses 50)         */
+    uint64_t max_events;       /* stop a photon (status 3) after this many cell
+                                  crossings plus interactions; 0 = no limit           */
 } orc_params;
 
 enum {
     ORC_EMITTED = 0, ORC_ESCAPED, ORC_ABSORBED, ORC_SCAT_HI, ORC_SCAT_DUST,
-    ORC_CROSSINGS, ORC_PEELS, ORC_UPAR_TRIES, ORC_PEEL_CROSSINGS, ORC_N_COUNTERS = 16
+    ORC_CROSSINGS, ORC_PEELS, ORC_UPAR_TRIES, ORC_PEEL_CROSSINGS, ORC_CAPPED,
+    ORC_N_COUNTERS = 16
 };
 
 typedef struct {
@@ -86,7 +89,7 @@ typedef struct {
     /* optional per-photon records indexed by (id - id_begin); NULL = off            */
     double *rec_x;             /* final lab x                                         */
     int32_t *rec_nscat;        /* executed HI scatterings                             */
-    int32_t *rec_status;       /* 1 escaped, 2 absorbed                               */
+    int32_t *rec_status;       /* 1 escaped, 2 absorbed, 3 stopped by max_events      */
     double *rec_pos;           /* 3 per photon, final position (cm)                   */
     double *rec_peel;          /* n_cams per photon, summed W exp(-tau)               */
 } orc_out;

@@ -195,6 +195,8 @@ static void run_photon(orc_job *J, uint64_t id, orc_tally *T)
     double tau = -log(orc_draw(&st));           /* eq. lnR */
 
     /* ---- ray tracing and scattering ---- */
+    uint64_t events = 0;
+    const uint64_t cap = p->max_events ? p->max_events : UINT64_MAX;
     for (;;) {
         int64_t ci = c.id;
         double x = comoving_x(C, ci, x_lab, k);
@@ -207,11 +209,13 @@ static void run_photon(orc_job *J, uint64_t id, orc_tally *T)
             tau -= tau_cell;
             for (int d = 0; d < 3; ++d) r[d] += l_exit * k[d];
             T->counters[ORC_CROSSINGS] += 1;
+            if (++events >= cap) { status = 3; break; }
             if (by_sphere || !orc_cross(g, &c, r, k, axis)) { status = 1; break; }
             continue;
         }
         double l = tau / k_tot;                 /* interaction inside this cell */
         for (int d = 0; d < 3; ++d) r[d] += l * k[d];
+        if (++events >= cap) { status = 3; break; }
 
         if (C->kd[ci] > 0.0 && orc_draw(&st) < C->kd[ci] / k_tot) {
             if (orc_draw(&st) >= g->dust_albedo) { status = 2; break; }
@@ -273,7 +277,8 @@ static void run_photon(orc_job *J, uint64_t id, orc_tally *T)
         tau = -log(orc_draw(&st));
     }
     if (status == 1) T->counters[ORC_ESCAPED] += 1;
-    else T->counters[ORC_ABSORBED] += 1;
+    else if (status == 2) T->counters[ORC_ABSORBED] += 1;
+    else T->counters[ORC_CAPPED] += 1;
 done:
     if (status == 1 && p->n_bins > 0)
         T->spectrum[bin_of(x_lab, p->x_min, p->x_max, p->n_bins)] += 1.0;

@@ -1,0 +1,733 @@
+// Host runtime of the transport library: grid upload and set-up, job
+// registration, batched persistent launches, tally read-back.  Implements the
+// C ABI declared in include/colt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "colt.h"
+#include "colt_internal.h"
+#include "colt_launch.h"
+
+using namespace colt;
+
+namespace {
+
+thread_local std::string g_error;
+thread_local hipEvent_t g_t0 = nullptr, g_t1 = nullptr;
+thread_local bool g_timed = false;
+
+colt_status fail(colt_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(COLT_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Device memory from the caller's allocator (or hipMalloc), remembered for release.
+struct DevMem {
+    colt_allocator alloc{};
+    bool custom = false;
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+
+    void *get(size_t n)
+    {
+        n = (n + 255) & ~size_t(255);
+        if (n == 0) n = 256;
+        void *p = nullptr;
+        if (custom) {
+            p = alloc.alloc(n, alloc.user);
+        } else if (hipMalloc(&p, n) != hipSuccess) {
+            p = nullptr;
+        }
+        if (p) {
+            ptrs.push_back(p);
+            bytes += n;
+        }
+        return p;
+    }
+    void release_all()
+    {
+        for (void *p : ptrs) {
+            if (custom) alloc.free(p, alloc.user);
+            else (void)hipFree(p);
+        }
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+// Reusable launch tables: device memory plus pinned host staging, recycled once
+// the event recorded after their launch has completed.
+struct LaunchBuf {
+    void *dev = nullptr;
+    void *host = nullptr;
+    size_t size = 0;
+    hipEvent_t done = nullptr;
+};
+std::mutex g_pool_mu;
+std::vector<LaunchBuf *> g_pool;
+
+LaunchBuf *acquire_launch_buf(size_t bytes)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (LaunchBuf *b : g_pool) {
+        if (b->size >= bytes && hipEventQuery(b->done) == hipSuccess) return b;
+    }
+    LaunchBuf *b = new LaunchBuf();
+    b->size = std::max<size_t>(bytes, 4096);
+    if (hipMalloc(&b->dev, b->size) != hipSuccess) { delete b; return nullptr; }
+    if (hipHostMalloc(&b->host, b->size, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(b->dev);
+        delete b;
+        return nullptr;
+    }
+    if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFree(b->dev);
+        (void)hipHostFree(b->host);
+        delete b;
+        return nullptr;
+    }
+    g_pool.push_back(b);
+    return b;
+}
+
+int cu_count()
+{
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            n = 256;
+    }
+    return n;
+}
+
+bool finite_pos(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct colt_grid_s {
+    DevMem mem;
+    GridView view{};               // cells/aux point at the FP64 records
+    void *rec_d = nullptr, *aux_d = nullptr, *rec_f = nullptr, *aux_f = nullptr;
+    int32_t kind = 0;
+    int64_t n_leaves = 0;
+    double dx_cm = 0.0;
+    double box_min[3] = {0, 0, 0};
+    std::atomic<int> jobs{0};
+    hipStream_t stream = nullptr;
+};
+
+struct colt_job_s {
+    DevMem mem;
+    colt_grid grid = nullptr;
+    JobView view{};
+    colt_job_params params{};
+    uint64_t launched = 0;
+    hipEvent_t done = nullptr;
+    bool ever_launched = false;
+};
+
+extern "C" {
+
+const char *colt_last_error(void) { return g_error.c_str(); }
+
+colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc, void *stream,
+                           colt_grid *out)
+{
+    if (!d || !out) return fail(COLT_ERR_ARG, "null descriptor or output");
+    *out = nullptr;
+    if (d->kind != 0 && d->kind != 1) return fail(COLT_ERR_ARG, "grid kind must be 0 or 1");
+    if (!d->n_HI || !d->T) return fail(COLT_ERR_ARG, "n_HI and T are required");
+    double ext[3];
+    for (int i = 0; i < 3; ++i) {
+        ext[i] = d->box_max[i] - d->box_min[i];
+        if (!(ext[i] > 0.0) || !finite_pos(ext[i]))
+            return fail(COLT_ERR_ARG, "box extent must be positive on every axis");
+    }
+    if (!(d->escape_radius >= 0.0)) return fail(COLT_ERR_ARG, "escape_radius must be >= 0");
+    if (!(d->dust_albedo >= 0.0 && d->dust_albedo <= 1.0))
+        return fail(COLT_ERR_ARG, "dust_albedo must lie in [0, 1]");
+    colt_grid g = new colt_grid_s();
+    g->kind = d->kind;
+    g->stream = (hipStream_t)stream;
+    if (alloc && alloc->alloc && alloc->free) {
+        g->mem.alloc = *alloc;
+        g->mem.custom = true;
+    }
+    for (int i = 0; i < 3; ++i) g->box_min[i] = d->box_min[i];
+
+    // leaf list (index into the caller's arrays) and device node table
+    std::vector<int64_t> leaf_src;
+    std::vector<int32_t> child_dev, base_dev;
+    int nb = 0;
+    if (d->kind == 0) {
+        if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0)
+            return delete g, fail(COLT_ERR_ARG, "Cartesian dimensions must be positive");
+        const int64_t n = (int64_t)d->nx * d->ny * d->nz;
+        if (d->n_cells != n)
+            return delete g, fail(COLT_ERR_ARG, "n_cells %lld != nx*ny*nz %lld",
+                                  (long long)d->n_cells, (long long)n);
+        if (n > INT32_MAX) return delete g, fail(COLT_ERR_ARG, "too many cells");
+        const double wx = ext[0] / d->nx, wy = ext[1] / d->ny, wz = ext[2] / d->nz;
+        if (std::fabs(wy / wx - 1.0) > 1e-9 || std::fabs(wz / wx - 1.0) > 1e-9)
+            return delete g, fail(COLT_ERR_ARG, "cells must be cubes");
+        g->dx_cm = wx;
+        g->view.n[0] = d->nx; g->view.n[1] = d->ny; g->view.n[2] = d->nz;
+        g->n_leaves = n;
+        leaf_src.resize(n);
+        for (int64_t i = 0; i < n; ++i) leaf_src[i] = i;
+    } else {
+        const int64_t nn = d->n_cells;
+        if (nn <= 0 || !d->child) return delete g, fail(COLT_ERR_ARG, "octree needs nodes and child");
+        if (nn > INT32_MAX / 2) return delete g, fail(COLT_ERR_ARG, "too many octree nodes");
+        if (std::fabs(ext[1] / ext[0] - 1.0) > 1e-9 || std::fabs(ext[2] / ext[0] - 1.0) > 1e-9)
+            return delete g, fail(COLT_ERR_ARG, "octree root box must be a cube");
+        // breadth-first walk: every node reached exactly once, depth per node
+        std::vector<int32_t> depth(nn, -1);
+        std::vector<int64_t> order;
+        order.reserve(nn);
+        depth[0] = 0;
+        order.push_back(0);
+        for (size_t h = 0; h < order.size(); ++h) {
+            const int64_t i = order[h];
+            const int32_t c = d->child[i];
+            if (c < 0) continue;
+            if ((int64_t)c + 7 >= nn || c <= 0)
+                return delete g, fail(COLT_ERR_ARG, "node %lld has child index %d out of range",
+                                      (long long)i, c);
+            for (int o = 0; o < 8; ++o) {
+                if (depth[c + o] >= 0)
+                    return delete g, fail(COLT_ERR_ARG, "node %d reached twice", c + o);
+                depth[c + o] = depth[i] + 1;
+                order.push_back(c + o);
+            }
+            if (depth[i] + 1 > 40) return delete g, fail(COLT_ERR_ARG, "octree deeper than 40");
+        }
+        if ((int64_t)order.size() != nn)
+            return delete g, fail(COLT_ERR_ARG, "%lld nodes unreachable from the root",
+                                  (long long)(nn - (int64_t)order.size()));
+        // base level: deepest level above which every node is refined (<= 7)
+        int min_leaf_depth = 1 << 30;
+        for (int64_t i = 0; i < nn; ++i)
+            if (d->child[i] < 0) min_leaf_depth = std::min(min_leaf_depth, depth[i]);
+        const int Lb = std::min(min_leaf_depth, 7);
+        nb = 1 << Lb;
+        g->dx_cm = ext[0] / nb;
+        g->view.n[0] = g->view.n[1] = g->view.n[2] = nb;
+        child_dev.assign(nn, 0);
+        for (int64_t i = 0; i < nn; ++i) {
+            if (d->child[i] >= 0) {
+                child_dev[i] = d->child[i];
+            } else {
+                child_dev[i] = -(int32_t)leaf_src.size() - 1;
+                leaf_src.push_back(i);
+            }
+        }
+        g->n_leaves = (int64_t)leaf_src.size();
+        base_dev.resize((size_t)nb * nb * nb);
+        for (int iz = 0; iz < nb; ++iz)
+            for (int iy = 0; iy < nb; ++iy)
+                for (int ix = 0; ix < nb; ++ix) {
+                    int64_t node = 0;
+                    for (int lv = Lb - 1; lv >= 0; --lv) {
+                        const int oct = ((ix >> lv) & 1) | (((iy >> lv) & 1) << 1) |
+                                        (((iz >> lv) & 1) << 2);
+                        node = d->child[node] + oct;
+                    }
+                    base_dev[((size_t)iz * nb + iy) * nb + ix] = (int32_t)node;
+                }
+    }
+    const int64_t nl = g->n_leaves;
+    // gather the gas of the leaves and validate it
+    std::vector<double> raw((size_t)nl * 7);
+    double *h_n = raw.data(), *h_T = h_n + nl, *h_kd = h_T + nl, *h_nl = h_kd + nl,
+           *h_v = h_nl + nl;
+    for (int64_t j = 0; j < nl; ++j) {
+        const int64_t i = leaf_src[j];
+        h_n[j] = d->n_HI[i];
+        h_T[j] = d->T[i];
+        h_kd[j] = d->k_dust ? d->k_dust[i] : 0.0;
+        h_nl[j] = d->atau_nl ? d->atau_nl[i] : 0.0;
+        for (int c = 0; c < 3; ++c) h_v[3 * j + c] = d->v ? d->v[3 * i + c] : 0.0;
+        if (!(h_n[j] >= 0.0) || !std::isfinite(h_n[j]) || !(h_T[j] > 0.0) ||
+            !std::isfinite(h_T[j]) || !(h_kd[j] >= 0.0) || !std::isfinite(h_kd[j]) ||
+            !(h_nl[j] >= 0.0) || !std::isfinite(h_nl[j]) || !std::isfinite(h_v[3 * j]) ||
+            !std::isfinite(h_v[3 * j + 1]) || !std::isfinite(h_v[3 * j + 2])) {
+            delete g;
+            return fail(COLT_ERR_ARG, "cell %lld has invalid gas values", (long long)i);
+        }
+    }
+    hipStream_t s = g->stream;
+    void *stage = g->mem.get(raw.size() * sizeof(double));
+    void *rd = g->mem.get((size_t)nl * sizeof(CellRec<double>));
+    void *ad = g->mem.get((size_t)nl * sizeof(CellAux<double>));
+    void *rf = g->mem.get((size_t)nl * sizeof(CellRec<float>));
+    void *af = g->mem.get((size_t)nl * sizeof(CellAux<float>));
+    void *dchild = nullptr, *dbase = nullptr;
+    if (d->kind == 1) {
+        dchild = g->mem.get(child_dev.size() * sizeof(int32_t));
+        dbase = g->mem.get(base_dev.size() * sizeof(int32_t));
+    }
+    if (!stage || !rd || !ad || !rf || !af || (d->kind == 1 && (!dchild || !dbase))) {
+        g->mem.release_all();
+        delete g;
+        return fail(COLT_ERR_NOMEM, "device allocation for the grid failed");
+    }
+    auto cleanup = [&]() { g->mem.release_all(); delete g; };
+    hipError_t e = hipMemcpyAsync(stage, raw.data(), raw.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && d->kind == 1) {
+        e = hipMemcpyAsync(dchild, child_dev.data(), child_dev.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dbase, base_dev.data(), base_dev.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s);
+    }
+    const double *sd = (const double *)stage;
+    if (e == hipSuccess)
+        e = launch_cell_setup(nl, sd, sd + nl, sd + 4 * nl, sd + 2 * nl, sd + 3 * nl, g->dx_cm,
+                              rd, ad, rf, af, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(COLT_ERR_HIP, "grid upload or set-up failed: %s", hipGetErrorString(e));
+    }
+    // the staging buffer is not needed any more
+    if (g->mem.custom) g->mem.alloc.free(stage, g->mem.alloc.user);
+    else (void)hipFree(stage);
+    g->mem.ptrs.erase(std::find(g->mem.ptrs.begin(), g->mem.ptrs.end(), stage));
+    g->mem.bytes -= ((raw.size() * sizeof(double) + 255) & ~size_t(255));
+
+    GridView &v = g->view;
+    v.kind = d->kind;
+    v.cells = rd;
+    v.aux = ad;
+    v.child = (const int32_t *)dchild;
+    v.base = (const int32_t *)dbase;
+    for (int i = 0; i < 3; ++i) v.centre[i] = 0.5 * ext[i] / g->dx_cm;
+    v.esc_r = d->escape_radius / g->dx_cm;
+    v.albedo = d->dust_albedo;
+    g->rec_d = rd; g->aux_d = ad; g->rec_f = rf; g->aux_f = af;
+    *out = g;
+    return COLT_OK;
+}
+
+colt_status colt_release_grid(colt_grid g)
+{
+    if (!g) return COLT_OK;
+    if (g->jobs.load() > 0) return fail(COLT_ERR_STATE, "grid still referenced by %d jobs",
+                                        g->jobs.load());
+    g->mem.release_all();
+    delete g;
+    return COLT_OK;
+}
+
+size_t colt_grid_bytes(colt_grid g) { return g ? g->mem.bytes : 0; }
+
+colt_status colt_grid_fields(colt_grid g, double *out)
+{
+    if (!g || !out) return fail(COLT_ERR_ARG, "null grid or output");
+    const int64_t n = g->n_leaves;
+    std::vector<CellRec<double>> rec(n);
+    std::vector<CellAux<double>> aux(n);
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    HIP_TRY(hipMemcpy(rec.data(), g->rec_d, n * sizeof(CellRec<double>), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(aux.data(), g->aux_d, n * sizeof(CellAux<double>), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) {
+        double *o = out + 10 * i;
+        o[0] = rec[i].k0 / g->dx_cm;
+        o[1] = rec[i].a;
+        o[2] = kVthRef / rec[i].s;
+        o[3] = rec[i].ux; o[4] = rec[i].uy; o[5] = rec[i].uz;
+        o[6] = rec[i].kd / g->dx_cm;
+        o[7] = rec[i].xcw;
+        o[8] = aux[i].g;
+        o[9] = aux[i].atau_nl;
+    }
+    return COLT_OK;
+}
+
+colt_status colt_emit(colt_grid g, const colt_source_desc *src, const colt_job_params *p,
+                      colt_job *out)
+{
+    if (!g || !src || !p || !out) return fail(COLT_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (p->precision != COLT_FP64 && p->precision != COLT_FP32_BULK)
+        return fail(COLT_ERR_ARG, "precision must be COLT_FP64 or COLT_FP32_BULK");
+    if (p->xcrit_mode < 0 || p->xcrit_mode > 2) return fail(COLT_ERR_ARG, "xcrit_mode 0..2");
+    if (p->xcrit_mode == 1 && !(p->atau0 >= 0.0)) return fail(COLT_ERR_ARG, "atau0 must be >= 0");
+    if (p->n_bins < 0 || (p->n_bins > 0 && !(p->x_max > p->x_min)))
+        return fail(COLT_ERR_ARG, "spectrum needs n_bins >= 0 and x_max > x_min");
+    if (p->n_cams < 0 || p->n_cams > kMaxCams) return fail(COLT_ERR_ARG, "0 <= n_cams <= 64");
+    if (p->n_cams > 0) {
+        if (!p->cam_dir) return fail(COLT_ERR_ARG, "cam_dir required");
+        if (p->cam_nbins < 0 || (p->cam_nbins > 0 && !(p->cam_xmax > p->cam_xmin)))
+            return fail(COLT_ERR_ARG, "camera spectrum needs cam_xmax > cam_xmin");
+        if (p->cam_npix < 0 || (p->cam_npix > 0 && !(p->cam_fov > 0.0)))
+            return fail(COLT_ERR_ARG, "camera images need cam_fov > 0");
+        if (!(p->tau_peel_max > 0.0)) return fail(COLT_ERR_ARG, "tau_peel_max must be > 0");
+    }
+    if (src->n_src < 1 || !src->pos) return fail(COLT_ERR_ARG, "at least one source position");
+    if (src->kind < 0 || src->kind > 2) return fail(COLT_ERR_ARG, "source kind 0..2");
+    if (src->kind != 2 && src->n_src != 1) return fail(COLT_ERR_ARG, "kinds 0, 1 take one source");
+    if (src->kind == 1 && !(src->sigma >= 0.0)) return fail(COLT_ERR_ARG, "sigma must be >= 0");
+    if (src->freq_mode != 0 && src->freq_mode != 1) return fail(COLT_ERR_ARG, "freq_mode 0 or 1");
+
+    colt_job j = new colt_job_s();
+    j->grid = g;
+    j->params = *p;
+    j->params.cam_dir = nullptr;
+    j->mem.alloc = g->mem.alloc;
+    j->mem.custom = g->mem.custom;
+    const int nc = p->n_cams;
+    // host tables: sources in grid units, cumulative weights, cameras
+    std::vector<double> hpos(3 * src->n_src), hcdf(src->n_src);
+    double wsum = 0.0;
+    for (int i = 0; i < src->n_src; ++i) {
+        const double w = src->weight ? src->weight[i] : 1.0;
+        if (!(w >= 0.0)) { delete j; return fail(COLT_ERR_ARG, "negative source weight"); }
+        wsum += w;
+        for (int c = 0; c < 3; ++c) hpos[3 * i + c] = (src->pos[3 * i + c] - g->box_min[c]) / g->dx_cm;
+    }
+    if (!(wsum > 0.0)) { delete j; return fail(COLT_ERR_ARG, "source weights sum to zero"); }
+    double acc = 0.0;
+    for (int i = 0; i < src->n_src; ++i) {
+        acc += src->weight ? src->weight[i] : 1.0;
+        hcdf[i] = acc / wsum;
+    }
+    std::vector<double> hcam(12 * std::max(nc, 1), 0.0);
+    for (int i = 0; i < nc; ++i) {
+        double dv[3] = {p->cam_dir[3 * i], p->cam_dir[3 * i + 1], p->cam_dir[3 * i + 2]};
+        const double n = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        if (!(n > 0.0) || !std::isfinite(n)) { delete j; return fail(COLT_ERR_ARG, "camera %d direction", i); }
+        for (double &c : dv) c /= n;
+        double up[3] = {0.0, 0.0, 1.0};
+        if (std::fabs(dv[2]) > 0.999) { up[1] = 1.0; up[2] = 0.0; }
+        double eu[3] = {up[1] * dv[2] - up[2] * dv[1], up[2] * dv[0] - up[0] * dv[2],
+                        up[0] * dv[1] - up[1] * dv[0]};
+        const double m = std::sqrt(eu[0] * eu[0] + eu[1] * eu[1] + eu[2] * eu[2]);
+        for (double &c : eu) c /= m;
+        const double ev[3] = {dv[1] * eu[2] - dv[2] * eu[1], dv[2] * eu[0] - dv[0] * eu[2],
+                              dv[0] * eu[1] - dv[1] * eu[0]};
+        double *o = &hcam[12 * i];
+        for (int c = 0; c < 3; ++c) {
+            o[c] = dv[c];
+            o[3 + c] = (dv[c] != 0.0) ? 1.0 / dv[c] : 0.0;
+            o[6 + c] = eu[c];
+            o[9 + c] = ev[c];
+        }
+    }
+    const uint64_t N = p->n_photons;
+    const size_t nbins = (size_t)p->n_bins + 2;
+    const size_t ncs = (size_t)nc * p->cam_nbins, nimg = (size_t)nc * p->cam_npix * p->cam_npix;
+    JobView &v = j->view;
+    v.g = g->view;
+    if (p->precision == COLT_FP32_BULK) { v.g.cells = g->rec_f; v.g.aux = g->aux_f; }
+    v.src_kind = src->kind;
+    v.n_src = src->n_src;
+    v.freq_mode = src->freq_mode;
+    v.sigma = src->sigma / g->dx_cm;
+    v.seed = p->seed;
+    v.n_photons = N;
+    v.max_events = p->max_events ? p->max_events : (uint64_t)1 << 62;
+    v.xcrit_mode = p->xcrit_mode;
+    v.recoil = p->recoil ? 1 : 0;
+    v.isotropic = p->isotropic ? 1 : 0;
+    v.n_bins = p->n_bins;
+    v.xcrit_global = (p->atau0 < 1.0) ? 0.0 : std::cbrt(p->atau0) / 5.0;
+    v.x_min = p->x_min;
+    v.x_max = p->x_max;
+    v.n_cams = nc;
+    v.cam_nbins = p->cam_nbins;
+    v.npix = p->cam_npix;
+    v.record = p->record ? 1 : 0;
+    v.cam_xmin = p->cam_xmin;
+    v.cam_xmax = p->cam_xmax;
+    v.fov = (p->cam_fov > 0.0) ? p->cam_fov / g->dx_cm : 1.0;
+    v.tau_peel_max = p->tau_peel_max;
+    v.dx_cm = g->dx_cm;
+    for (int c = 0; c < 3; ++c) v.box_min_cm[c] = g->box_min[c];
+
+    DevMem &m = j->mem;
+    double *d_pos = (double *)m.get(hpos.size() * sizeof(double));
+    double *d_cdf = (double *)m.get(hcdf.size() * sizeof(double));
+    double *d_cam = (double *)m.get(hcam.size() * sizeof(double));
+    v.spectrum = (unsigned long long *)m.get(nbins * sizeof(unsigned long long));
+    v.cam_spec = (double *)m.get(std::max<size_t>(ncs, 1) * sizeof(double));
+    v.cam_img = (double *)m.get(std::max<size_t>(nimg, 1) * sizeof(double));
+    v.counters = (unsigned long long *)m.get(kCounterSlots * kNumCounters * sizeof(unsigned long long));
+    bool ok = d_pos && d_cdf && d_cam && v.spectrum && v.cam_spec && v.cam_img && v.counters;
+    if (p->record && ok) {
+        const size_t n1 = std::max<uint64_t>(N, 1);
+        v.rec_x = (double *)m.get(n1 * sizeof(double));
+        v.rec_nscat = (int32_t *)m.get(n1 * sizeof(int32_t));
+        v.rec_status = (int32_t *)m.get(n1 * sizeof(int32_t));
+        v.rec_pos = (double *)m.get(3 * n1 * sizeof(double));
+        v.rec_peel = (double *)m.get(std::max<size_t>(n1 * nc, 1) * sizeof(double));
+        ok = v.rec_x && v.rec_nscat && v.rec_status && v.rec_pos && v.rec_peel;
+    }
+    if (!ok) {
+        m.release_all();
+        delete j;
+        return fail(COLT_ERR_NOMEM, "device allocation for the job failed");
+    }
+    v.src_pos = d_pos;
+    v.src_cdf = d_cdf;
+    v.cam = d_cam;
+    hipStream_t s = g->stream;
+    hipError_t e = hipMemcpyAsync(d_pos, hpos.data(), hpos.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_cdf, hcdf.data(), hcdf.size() * sizeof(double),
+                                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_cam, hcam.data(), hcam.size() * sizeof(double),
+                                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(v.spectrum, 0, nbins * 8, s);
+    if (e == hipSuccess) e = hipMemsetAsync(v.cam_spec, 0, std::max<size_t>(ncs, 1) * 8, s);
+    if (e == hipSuccess) e = hipMemsetAsync(v.cam_img, 0, std::max<size_t>(nimg, 1) * 8, s);
+    if (e == hipSuccess) e = hipMemsetAsync(v.counters, 0, kCounterSlots * kNumCounters * 8, s);
+    if (e == hipSuccess && p->record)
+        e = hipMemsetAsync(v.rec_peel, 0, std::max<size_t>(std::max<uint64_t>(N, 1) * nc, 1) * 8, s);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&j->done, hipEventDisableTiming);
+    // host tables must outlive the asynchronous copies
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        m.release_all();
+        delete j;
+        return fail(COLT_ERR_HIP, "job set-up failed: %s", hipGetErrorString(e));
+    }
+    g->jobs.fetch_add(1);
+    *out = j;
+    return COLT_OK;
+}
+
+size_t colt_job_bytes(colt_job j) { return j ? j->mem.bytes : 0; }
+
+colt_status colt_job_status(colt_job j, uint64_t *launched, uint64_t *total)
+{
+    if (!j) return fail(COLT_ERR_ARG, "null job");
+    if (launched) *launched = j->launched;
+    if (total) *total = j->params.n_photons;
+    return COLT_OK;
+}
+
+void colt_release_job(colt_job j)
+{
+    if (!j) return;
+    if (j->ever_launched) (void)hipEventSynchronize(j->done);
+    if (j->done) (void)hipEventDestroy(j->done);
+    j->mem.release_all();
+    if (j->grid) j->grid->jobs.fetch_sub(1);
+    delete j;
+}
+
+colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
+                           void *stream)
+{
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(COLT_ERR_ARG, "bad job list");
+    hipStream_t s = (hipStream_t)stream;
+    int block = (launch && launch->block) ? launch->block : 256;
+    if (block < 64 || block > 256 || block % 64)
+        return fail(COLT_ERR_ARG, "block must be 64, 128, 192 or 256");
+    const uint64_t quota = launch ? launch->photons_per_job : 0;
+    const bool timed = launch && launch->time_kernel;
+    for (int i = 0; i < n_jobs; ++i) {
+        if (!jobs[i]) return fail(COLT_ERR_ARG, "null job %d", i);
+        for (int k = 0; k < i; ++k)
+            if (jobs[k] == jobs[i]) return fail(COLT_ERR_ARG, "job %d listed twice", i);
+    }
+    for (int prec = 0; prec < 2; ++prec) {
+        std::vector<JobView> views;
+        std::vector<uint64_t> prefix(1, 0), first;
+        std::vector<colt_job> members;
+        for (int i = 0; i < n_jobs; ++i) {
+            colt_job j = jobs[i];
+            if (j->params.precision != prec) continue;
+            const uint64_t left = j->params.n_photons - j->launched;
+            const uint64_t take = (quota && quota < left) ? quota : left;
+            if (take == 0) continue;
+            views.push_back(j->view);
+            first.push_back(j->launched);
+            prefix.push_back(prefix.back() + take);
+            members.push_back(j);
+        }
+        if (members.empty()) continue;
+        const int nj = (int)members.size();
+        const size_t off_prefix = ((sizeof(JobView) * nj) + 255) & ~size_t(255);
+        const size_t off_first = off_prefix + ((8 * (nj + 1) + 255) & ~size_t(255));
+        const size_t off_queue = off_first + ((8 * nj + 255) & ~size_t(255));
+        const size_t bytes = off_queue + 256;
+        LaunchBuf *b = acquire_launch_buf(bytes);
+        if (!b) return fail(COLT_ERR_NOMEM, "launch table allocation failed");
+        char *h = (char *)b->host;
+        std::memcpy(h, views.data(), sizeof(JobView) * nj);
+        std::memcpy(h + off_prefix, prefix.data(), 8 * (nj + 1));
+        std::memcpy(h + off_first, first.data(), 8 * nj);
+        std::memset(h + off_queue, 0, 256);
+        HIP_TRY(hipMemcpyAsync(b->dev, b->host, bytes, hipMemcpyHostToDevice, s));
+        LaunchView L{};
+        char *dv = (char *)b->dev;
+        L.jobs = (const JobView *)dv;
+        L.prefix = (const uint64_t *)(dv + off_prefix);
+        L.first_id = (const uint64_t *)(dv + off_first);
+        L.queue = (unsigned long long *)(dv + off_queue);
+        L.n_jobs = nj;
+        L.total = prefix.back();
+        int per_cu = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 0;
+        if (per_cu <= 0) {
+            HIP_TRY(transport_occupancy(prec, block, &per_cu));
+            if (per_cu <= 0) per_cu = 1;
+        }
+        const uint64_t lanes_needed = (L.total + 63) / 64 * 64;
+        uint64_t grid = (uint64_t)cu_count() * per_cu;
+        const uint64_t grid_needed = (lanes_needed + block - 1) / block;
+        if (grid > grid_needed) grid = grid_needed;
+        if (grid < 1) grid = 1;
+        if (timed) {
+            if (!g_t0) {
+                HIP_TRY(hipEventCreate(&g_t0));
+                HIP_TRY(hipEventCreate(&g_t1));
+            }
+            HIP_TRY(hipEventRecord(g_t0, s));
+        }
+        HIP_TRY(launch_transport(prec, L, (int)grid, block, s));
+        if (timed) {
+            HIP_TRY(hipEventRecord(g_t1, s));
+            g_timed = true;
+        }
+        HIP_TRY(hipEventRecord(b->done, s));
+        for (int i = 0; i < nj; ++i) {
+            colt_job j = members[i];
+            j->launched += prefix[i + 1] - prefix[i];
+            HIP_TRY(hipEventRecord(j->done, s));
+            j->ever_launched = true;
+        }
+    }
+    return COLT_OK;
+}
+
+double colt_last_kernel_ms(void)
+{
+    if (!g_timed) return -1.0;
+    float ms = -1.0f;
+    if (hipEventSynchronize(g_t1) != hipSuccess) return -1.0;
+    if (hipEventElapsedTime(&ms, g_t0, g_t1) != hipSuccess) return -1.0;
+    return ms;
+}
+
+colt_status colt_tally(colt_job j, colt_tally_out *o, int32_t wait)
+{
+    if (!j || !o) return fail(COLT_ERR_ARG, "null job or output");
+    if (j->ever_launched) {
+        if (wait) {
+            HIP_TRY(hipEventSynchronize(j->done));
+        } else {
+            hipError_t q = hipEventQuery(j->done);
+            if (q == hipErrorNotReady) return fail(COLT_ERR_BUSY, "job still running");
+            if (q != hipSuccess) return fail(COLT_ERR_HIP, "event query: %s", hipGetErrorString(q));
+        }
+    } else {
+        HIP_TRY(hipStreamSynchronize(j->grid->stream));
+    }
+    const colt_job_params &p = j->params;
+    const JobView &v = j->view;
+    const size_t nbins = (size_t)p.n_bins + 2;
+    if (o->spectrum) {
+        std::vector<unsigned long long> tmp(nbins);
+        HIP_TRY(hipMemcpy(tmp.data(), v.spectrum, nbins * 8, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < nbins; ++i) o->spectrum[i] = (double)tmp[i];
+    }
+    const size_t ncs = (size_t)p.n_cams * p.cam_nbins;
+    const size_t nimg = (size_t)p.n_cams * p.cam_npix * p.cam_npix;
+    if (o->cam_spec && ncs) HIP_TRY(hipMemcpy(o->cam_spec, v.cam_spec, ncs * 8, hipMemcpyDeviceToHost));
+    if (o->cam_img && nimg) HIP_TRY(hipMemcpy(o->cam_img, v.cam_img, nimg * 8, hipMemcpyDeviceToHost));
+    {
+        std::vector<unsigned long long> c(kCounterSlots * kNumCounters);
+        HIP_TRY(hipMemcpy(c.data(), v.counters, c.size() * 8, hipMemcpyDeviceToHost));
+        for (int i = 0; i < COLT_N_COUNTERS; ++i) {
+            uint64_t t = 0;
+            for (int s = 0; s < kCounterSlots; ++s) t += c[s * kNumCounters + i];
+            o->counters[i] = t;
+        }
+    }
+    if (p.record) {
+        const size_t N = p.n_photons;
+        if (N) {
+            if (o->rec_x) HIP_TRY(hipMemcpy(o->rec_x, v.rec_x, N * 8, hipMemcpyDeviceToHost));
+            if (o->rec_nscat) HIP_TRY(hipMemcpy(o->rec_nscat, v.rec_nscat, N * 4, hipMemcpyDeviceToHost));
+            if (o->rec_status) HIP_TRY(hipMemcpy(o->rec_status, v.rec_status, N * 4, hipMemcpyDeviceToHost));
+            if (o->rec_pos) HIP_TRY(hipMemcpy(o->rec_pos, v.rec_pos, 3 * N * 8, hipMemcpyDeviceToHost));
+            if (o->rec_peel && p.n_cams)
+                HIP_TRY(hipMemcpy(o->rec_peel, v.rec_peel, N * p.n_cams * 8, hipMemcpyDeviceToHost));
+        }
+    }
+    return COLT_OK;
+}
+
+colt_status colt_eval_voigt(int32_t precision, const double *a, const double *x, int64_t n,
+                            double *out, void *stream)
+{
+    if (n < 0 || (n > 0 && (!a || !x || !out))) return fail(COLT_ERR_ARG, "bad arrays");
+    if (precision != 0 && precision != 1) return fail(COLT_ERR_ARG, "precision 0 or 1");
+    if (n == 0) return COLT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double *d = nullptr;
+    HIP_TRY(hipMalloc(&d, 3 * n * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(d, a, n * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + n, x, n * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_voigt(precision, n, d, d + n, d + 2 * n, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d + 2 * n, n * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(COLT_ERR_HIP, "voigt check failed: %s", hipGetErrorString(e));
+    return COLT_OK;
+}
+
+colt_status colt_sample(int32_t what, int32_t precision, double p0, double p1, double p2,
+                        uint64_t seed, int64_t n, double *out, int32_t *draws, void *stream)
+{
+    if (what < 0 || what > 3 || n < 0 || (n > 0 && !out) || (what == 0 && n > 0 && !draws))
+        return fail(COLT_ERR_ARG, "bad sampler request");
+    if (precision != 0 && precision != 1) return fail(COLT_ERR_ARG, "precision 0 or 1");
+    if (what == 3 && !(p0 >= 1.0 && p0 <= 4096.0)) return fail(COLT_ERR_ARG, "1..4096 draws");
+    if (n == 0) return COLT_OK;
+    const int64_t per = (what == 1) ? 2 : ((what == 3) ? (int64_t)p0 : 1);
+    hipStream_t s = (hipStream_t)stream;
+    double *d = nullptr;
+    int32_t *dd = nullptr;
+    HIP_TRY(hipMalloc(&d, n * per * sizeof(double)));
+    hipError_t e = hipMalloc(&dd, n * sizeof(int32_t));
+    if (e == hipSuccess) e = launch_sample(precision, what, p0, p1, p2, seed, n, d, dd, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d, n * per * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && what == 0)
+        e = hipMemcpyAsync(draws, dd, n * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (dd) (void)hipFree(dd);
+    if (e != hipSuccess) return fail(COLT_ERR_HIP, "sampler check failed: %s", hipGetErrorString(e));
+    return COLT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,334 @@
+// Device building blocks of the Lyman-alpha transport: counter-based random
+// numbers, H(a,x), x_cw, and the scattering samplers, in FP64 or FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "colt_internal.h"
+
+namespace colt {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.77245385090551602730;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products,
+// a word swap and a xor with the round key; the key advances by the Weyl
+// constants after every round.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
+                                              uint32_t &c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Per-photon stream: uniform k of photon `id` under key `seed` uses counter
+// block (k / per_block) of the photon's counter space.  FP64 takes 53 bits
+// from a word pair (two draws per block); FP32 takes one word per draw (four
+// per block).  The last block's unused words are cached in registers.
+template <typename R>
+struct Rng;
+
+template <>
+struct Rng<double> {
+    uint32_t key0, key1, id0, id1;
+    uint64_t k;
+    uint32_t w2, w3;
+    __device__ void init(uint64_t seed, uint64_t id)
+    {
+        key0 = (uint32_t)seed; key1 = (uint32_t)(seed >> 32);
+        id0 = (uint32_t)id; id1 = (uint32_t)(id >> 32);
+        k = 0;
+    }
+    __device__ __forceinline__ double next()
+    {
+        uint32_t lo, hi;
+        if ((k & 1) == 0) {
+            const uint64_t b = k >> 1;
+            uint32_t c0 = (uint32_t)b, c1 = (uint32_t)(b >> 32), c2 = id0, c3 = id1;
+            philox4x32_10(c0, c1, c2, c3, key0, key1);
+            lo = c0; hi = c1; w2 = c2; w3 = c3;
+        } else {
+            lo = w2; hi = w3;
+        }
+        ++k;
+        const uint64_t m = ((((uint64_t)hi) << 32) | lo) >> 11;
+        return ((double)m + 1.0) * 0x1.0p-53;
+    }
+};
+
+template <>
+struct Rng<float> {
+    uint32_t key0, key1, id0, id1;
+    uint64_t k;
+    uint32_t w1, w2, w3;
+    __device__ void init(uint64_t seed, uint64_t id)
+    {
+        key0 = (uint32_t)seed; key1 = (uint32_t)(seed >> 32);
+        id0 = (uint32_t)id; id1 = (uint32_t)(id >> 32);
+        k = 0;
+    }
+    __device__ __forceinline__ float next()
+    {
+        const uint32_t j = (uint32_t)k & 3u;
+        uint32_t w;
+        if (j == 0) {
+            const uint64_t b = k >> 2;
+            uint32_t c0 = (uint32_t)b, c1 = (uint32_t)(b >> 32), c2 = id0, c3 = id1;
+            philox4x32_10(c0, c1, c2, c3, key0, key1);
+            w = c0; w1 = c1; w2 = c2; w3 = c3;
+        } else {
+            w = (j == 1) ? w1 : ((j == 2) ? w2 : w3);
+        }
+        ++k;
+        // (0, 1]: w 2^-32 + 2^-33, rounded to float
+        return __builtin_fmaf((float)w, 0x1.0p-32f, 0x1.0p-33f);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Elementary functions per precision.  FP64 uses the correctly-behaved double
+// library functions; FP32 uses the hardware transcendental units (exp2, log2,
+// sin/cos of revolutions).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Fn;
+
+template <>
+struct Fn<double> {
+    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    static __device__ __forceinline__ double log(double x) { return ::log(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double cbrt(double x) { return ::cbrt(x); }
+    static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
+    static __device__ __forceinline__ double tan(double x) { return ::tan(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    // cos and sin of 2 pi R
+    static __device__ __forceinline__ void cossin2pi(double R, double &c, double &s)
+    {
+        const double ang = 2.0 * kPi * R;
+        c = ::cos(ang);
+        s = ::sin(ang);
+    }
+};
+
+template <>
+struct Fn<float> {
+    static __device__ __forceinline__ float exp(float x)
+    {
+        return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
+    }
+    static __device__ __forceinline__ float log(float x)
+    {
+        return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
+    }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ float cbrt(float x) { return ::cbrtf(x); }
+    static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
+    static __device__ __forceinline__ float div(float a, float b)
+    {
+        return a * __builtin_amdgcn_rcpf(b);
+    }
+    static __device__ __forceinline__ void cossin2pi(float R, float &c, float &s)
+    {
+        c = __builtin_amdgcn_cosf(R);
+        s = __builtin_amdgcn_sinf(R);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// H(a, x) to first order in a, three regions in z = x^2 with the continued
+// fractions and coefficients of the paper's appendix (eq. AB, table AB).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R voigt_H(R a, R x)
+{
+    using F = Fn<R>;
+    const R z = x * x;
+    if (z <= R(3)) {
+        const R cf = F::div(R(286.9341762324778),
+                            z - R(19.05706700907019) +
+                                F::div(R(28.22644017233441),
+                                       z - R(9.526399802414186) +
+                                           F::div(R(35.29217026286130),
+                                                  z - R(0.8681020834678775))));
+        return F::exp(-z) * (R(1) - a * (R(15.75328153963877) + cf));
+    } else if (z < R(25)) {
+        const R cf = F::div(
+            R(0.5403095364583999),
+            z - R(2.676724102580895) +
+                F::div(R(12.82026082606220),
+                       z + R(3.21166435627278) +
+                           F::div(R(32.032981933420),
+                                  z - R(9.0328158696) +
+                                      F::div(R(23.7489999060), z - R(1.82106170570)))));
+        return F::exp(-z) + a * (R(0.0003300469163682737) + cf);
+    } else {
+        return F::div(F::div(a, R(kSqrtPi)),
+                      z - R(1.5) - F::div(R(1.5), z - R(3.5) - F::div(R(5), z - R(5.5))));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Parallel atom velocity u_par from f(u) ~ exp(-u^2)/(a^2+(x-u)^2)
+// (Sec. 3.2.3): Lorentzian proposal for |x| <= 1; two-part comparison
+// function split at u0 for 1 < |x| < 9 (u0,core below x_cw, u0,wing above),
+// redrawing the part after each rejection; Gaussian of mean 1/x for |x| >= 9.
+// Draw order: per attempt (theta, accept) or (part, theta, accept).
+// The FP64 form follows the paper's expressions literally; the FP32 form
+// evaluates the same quantities through phi = theta + pi/2, which keeps the
+// angles near -pi/2 accurate in single precision.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R draw_upar(R a, R x, R xcw, Rng<R> &rng, uint32_t &tries)
+{
+    using F = Fn<R>;
+    const R sgn = (x < R(0)) ? R(-1) : R(1);
+    const R X = (x < R(0)) ? -x : x;
+    R u;
+    if (X <= R(1)) {
+        for (;;) {
+            const R Rth = rng.next();
+            if constexpr (sizeof(R) == 8) {
+                u = a * F::tan(kPi * (Rth - 0.5)) + X;
+            } else {
+                // tan(pi (R - 1/2)) = -cos(pi R) / sin(pi R)
+                float c, s;
+                F::cossin2pi(0.5f * Rth, c, s);
+                u = X - a * F::div(c, s);
+            }
+            const R Racc = rng.next();
+            ++tries;
+            if (Racc < F::exp(-u * u)) break;
+        }
+    } else if (X < R(9)) {
+        R u0;
+        if (X < xcw)
+            u0 = X - F::div(R(1), X + F::div(F::exp(R(1) - X * X), a));
+        else
+            u0 = xcw - F::div(R(1), xcw) + R(0.15) * (X - xcw);
+        const R e0 = F::exp(-u0 * u0);
+        if constexpr (sizeof(R) == 8) {
+            const double theta0 = ::atan((u0 - X) / a);
+            const double p = (theta0 + kPi / 2.0) /
+                             ((1.0 - e0) * theta0 + (1.0 + e0) * kPi / 2.0);
+            for (;;) {
+                const double Rp = rng.next();
+                const double Rth = rng.next();
+                double acc;
+                if (Rp <= p) {
+                    const double theta = -kPi / 2.0 + Rth * (theta0 + kPi / 2.0);
+                    u = a * ::tan(theta) + X;
+                    acc = ::exp(-u * u);
+                } else {
+                    const double theta = theta0 + Rth * (kPi / 2.0 - theta0);
+                    u = a * ::tan(theta) + X;
+                    acc = ::exp(u0 * u0 - u * u);
+                }
+                const double Racc = rng.next();
+                ++tries;
+                if (Racc < acc) break;
+            }
+        } else {
+            // phi0 = theta0 + pi/2 = atan(a / (X - u0)), u0 < X
+            const float phi0 = F::atan(F::div(a, X - u0));
+            const float p = F::div(phi0, phi0 + e0 * (float(kPi) - phi0));
+            const float u0sq = u0 * u0;
+            for (;;) {
+                const float Rp = rng.next();
+                const float Rth = rng.next();
+                // theta = phi - pi/2, a tan(theta) = -a cos(phi) / sin(phi)
+                const bool lower = Rp <= p;
+                const float phi = lower ? Rth * phi0 : phi0 + Rth * (float(kPi) - phi0);
+                float c, s;
+                F::cossin2pi(phi * float(0.5 / kPi), c, s);
+                u = X - a * F::div(c, s);
+                const float acc = lower ? F::exp(-u * u) : F::exp(u0sq - u * u);
+                const float Racc = rng.next();
+                ++tries;
+                if (Racc < acc) break;
+            }
+        }
+    } else {
+        const R R1 = rng.next();
+        const R R2 = rng.next();
+        R c, s;
+        F::cossin2pi(R2, c, s);
+        u = F::div(R(1), X) + F::sqrt(-F::log(R1)) * c;
+    }
+    return sgn * u;
+}
+
+// Perpendicular components: Box-Muller on exp(-u^2)/sqrt(pi), truncated below
+// the core-skipping frequency (Sec. 3.2.4).
+template <typename R>
+__device__ __forceinline__ void draw_uperp(R xc, Rng<R> &rng, R &u1, R &u2)
+{
+    using F = Fn<R>;
+    const R R1 = rng.next();
+    const R R2 = rng.next();
+    const R rho = F::sqrt(xc * xc - F::log(R1));
+    R c, s;
+    F::cossin2pi(R2, c, s);
+    u1 = rho * c;
+    u2 = rho * s;
+}
+
+// Cosine of the scattering angle for W(mu) ~ 1 + rW mu^2 (eq. phaseW) by
+// inverting its cubic CDF with Cardano's formula.
+template <typename R>
+__device__ __forceinline__ R draw_mu(R rW, Rng<R> &rng)
+{
+    using F = Fn<R>;
+    const R Rm = rng.next();
+    if (rW == R(0)) return R(2) * Rm - R(1);
+    const R p = F::div(R(3), rW);
+    const R q = (R(1) + p) * (R(1) - R(2) * Rm);
+    const R D = R(0.25) * q * q + F::div(p * p * p, R(27));
+    const R aq = (q < R(0)) ? -q : q;
+    R c = F::cbrt(R(0.5) * aq + F::sqrt(D));
+    if (q > R(0)) c = -c;
+    R mu = c - F::div(p, R(3) * c);
+    mu = (mu > R(1)) ? R(1) : mu;
+    mu = (mu < R(-1)) ? R(-1) : mu;
+    return mu;
+}
+
+// Orthonormal e1, e2 perpendicular to unit k: e1 ~ k x z (k x x when |k_z| > 0.9).
+template <typename R>
+__device__ __forceinline__ void perp_basis(const R k[3], R e1[3], R e2[3])
+{
+    using F = Fn<R>;
+    const R kz = (k[2] < R(0)) ? -k[2] : k[2];
+    if (kz <= R(0.9)) {
+        const R n = F::sqrt(k[0] * k[0] + k[1] * k[1]);
+        e1[0] = F::div(k[1], n); e1[1] = F::div(-k[0], n); e1[2] = R(0);
+    } else {
+        const R n = F::sqrt(k[1] * k[1] + k[2] * k[2]);
+        e1[0] = R(0); e1[1] = F::div(k[2], n); e1[2] = F::div(-k[1], n);
+    }
+    e2[0] = k[1] * e1[2] - k[2] * e1[1];
+    e2[1] = k[2] * e1[0] - k[0] * e1[2];
+    e2[2] = k[0] * e1[1] - k[1] * e1[0];
+}
+
+template <typename R>
+__device__ __forceinline__ R xcrit_of(R atau0)
+{
+    return (atau0 < R(1)) ? R(0) : Fn<R>::div(Fn<R>::cbrt(atau0), R(5));
+}
+
+}  // namespace colt

@@ -1,0 +1,708 @@
+// HIP kernels of the Lyman-alpha transport library (gfx950).
+//
+//  k_cell_setup   per-cell line quantities from (n_HI, T, v, k_dust)
+//  k_transport    persistent photon-pool transport: each lane carries one
+//                 photon through emission, cell-by-cell ray tracing,
+//                 scattering and next-event tallies; a lane whose photon has
+//                 escaped or been absorbed takes the next photon from a shared
+//                 queue (one atomic per wave per refill).
+//  k_voigt, k_sample   device checks of H(a,x) and of the samplers.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "colt_device.h"
+#include "colt_internal.h"
+#include "colt_launch.h"
+
+namespace colt {
+
+// ---------------------------------------------------------------------------
+// Cell set-up (Sec. 2): T4 = T/1e4, v_th = 12.85 T4^1/2 km/s, a = 4.702e-4
+// T4^-1/2, sigma0 = 5.898e-14 T4^-1/2 cm^2, recoil g = 2.536e-4 T4^-1/2; the
+// core-wing crossover x_cw from its rational fit in ln a (Sec. 3.2.2).
+// Opacities are stored per grid unit (dx_cm), velocities in units of v_th.
+// ---------------------------------------------------------------------------
+__global__ void k_cell_setup(int64_t n, const double *__restrict__ n_HI,
+                             const double *__restrict__ T, const double *__restrict__ v,
+                             const double *__restrict__ k_dust,
+                             const double *__restrict__ atau_nl, double dx_cm,
+                             CellRec<double> *__restrict__ rd, CellAux<double> *__restrict__ ad,
+                             CellRec<float> *__restrict__ rf, CellAux<float> *__restrict__ af)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double T4 = T[i] / 1.0e4;
+    const double sq = ::sqrt(T4);
+    const double vth = kVthRef * sq;
+    const double a = 4.702e-4 / sq;
+    const double sigma0 = 5.898e-14 / sq;
+    const double k0 = n_HI[i] * sigma0;
+    const double xcw = 6.9184721 + 81.766279 / (::log(a) - 14.651253);
+    const double g = 2.536e-4 / sq;
+    const double kd = k_dust ? k_dust[i] : 0.0;
+    const double vx = v ? v[3 * i] : 0.0, vy = v ? v[3 * i + 1] : 0.0, vz = v ? v[3 * i + 2] : 0.0;
+    CellRec<double> c;
+    c.k0 = k0 * dx_cm;
+    c.a = a;
+    c.s = kVthRef / vth;
+    c.kd = kd * dx_cm;
+    c.ux = vx / vth;
+    c.uy = vy / vth;
+    c.uz = vz / vth;
+    c.xcw = xcw;
+    rd[i] = c;
+    CellAux<double> x;
+    x.g = g;
+    x.atau_nl = atau_nl ? atau_nl[i] : 0.0;
+    ad[i] = x;
+    CellRec<float> cf;
+    cf.k0 = (float)c.k0; cf.a = (float)c.a; cf.s = (float)c.s; cf.kd = (float)c.kd;
+    cf.ux = (float)c.ux; cf.uy = (float)c.uy; cf.uz = (float)c.uz; cf.xcw = (float)c.xcw;
+    rf[i] = cf;
+    CellAux<float> xf;
+    xf.g = (float)x.g;
+    xf.atau_nl = (float)x.atau_nl;
+    af[i] = xf;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry.  Cells are half-open; a point on a face belongs to the cell the
+// photon moves into.  Positions are in grid units from the lower box corner.
+// ---------------------------------------------------------------------------
+struct CellBox {
+    double lo[3];
+    double size;
+    int32_t cell;
+};
+
+__device__ __forceinline__ int side_of(double r, double mid, double k)
+{
+    return (r > mid) ? 1 : ((r < mid) ? 0 : ((k < 0.0) ? 0 : 1));
+}
+
+// Finds the cell holding r for a photon moving along k; false if r is outside
+// the domain (box or escape sphere).
+__device__ bool locate(const GridView &g, const double r[3], const double k[3], CellBox &c)
+{
+    int ib[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double n = (double)g.n[d];
+        if (r[d] < 0.0 || r[d] > n) return false;
+        if (r[d] == n && k[d] >= 0.0) return false;
+        if (r[d] == 0.0 && k[d] < 0.0) return false;
+        const double f = ::floor(r[d]);
+        int i = (int)f;
+        if (r[d] == f && k[d] < 0.0) i -= 1;
+        i = (i < 0) ? 0 : ((i >= g.n[d]) ? g.n[d] - 1 : i);
+        ib[d] = i;
+    }
+    if (g.esc_r > 0.0) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) d2 += (r[d] - g.centre[d]) * (r[d] - g.centre[d]);
+        if (d2 >= g.esc_r * g.esc_r) return false;
+    }
+    const int flat = (ib[2] * g.n[1] + ib[1]) * g.n[0] + ib[0];
+    c.lo[0] = ib[0]; c.lo[1] = ib[1]; c.lo[2] = ib[2];
+    c.size = 1.0;
+    if (g.kind == 0) {
+        c.cell = flat;
+        return true;
+    }
+    int node = g.base[flat];
+    int ch = g.child[node];
+    double size = 1.0;
+    while (ch >= 0) {
+        const double half = 0.5 * size;
+        int oct = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int b = side_of(r[d], c.lo[d] + half, k[d]);
+            if (b) c.lo[d] += half;
+            oct |= b << d;
+        }
+        node = ch + oct;
+        size = half;
+        ch = g.child[node];
+    }
+    c.size = size;
+    c.cell = -ch - 1;
+    return true;
+}
+
+// Distance to the exit of cell c along k (inverse components ik), nearest face
+// first-axis on ties, or to the escape sphere (by_sphere) if nearer or equal.
+__device__ __forceinline__ double exit_distance(const GridView &g, const CellBox &c,
+                                                const double r[3], const double k[3],
+                                                const double ik[3], int &axis, bool &by_sphere)
+{
+    double best = __builtin_inf();
+    axis = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double t;
+        if (k[d] > 0.0) t = (c.lo[d] + c.size - r[d]) * ik[d];
+        else if (k[d] < 0.0) t = (c.lo[d] - r[d]) * ik[d];
+        else continue;
+        t = (t < 0.0) ? 0.0 : t;
+        if (t < best) { best = t; axis = d; }
+    }
+    by_sphere = false;
+    if (g.esc_r > 0.0) {
+        double b = 0.0, rr = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double rc = r[d] - g.centre[d];
+            b += rc * k[d];
+            rr += rc * rc;
+        }
+        const double disc = b * b - (rr - g.esc_r * g.esc_r);
+        double t = (disc > 0.0) ? -b + ::sqrt(disc) : 0.0;
+        t = (t < 0.0) ? 0.0 : t;
+        if (t <= best) { best = t; by_sphere = true; }
+    }
+    return best;
+}
+
+// Moves a photon on the exit face of `axis` into the next cell; false if it
+// leaves the domain.
+__device__ __forceinline__ bool cross(const GridView &g, CellBox &c, double r[3],
+                                      const double k[3], int axis)
+{
+    r[axis] = (k[axis] > 0.0) ? c.lo[axis] + c.size : c.lo[axis];
+    if (g.kind == 0) {
+        const int step = (k[axis] > 0.0) ? 1 : -1;
+        const int i = (int)c.lo[axis] + step;
+        if (i < 0 || i >= g.n[axis]) return false;
+        c.lo[axis] = (double)i;
+        const int stride = (axis == 0) ? 1 : ((axis == 1) ? g.n[0] : g.n[0] * g.n[1]);
+        c.cell += step * stride;
+        return true;
+    }
+    return locate(g, r, k, c);
+}
+
+__device__ __forceinline__ double min_face_distance(const CellBox &c, const double r[3])
+{
+    double m = __builtin_inf();
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double lo = r[d] - c.lo[d], hi = c.lo[d] + c.size - r[d];
+        m = (lo < m) ? lo : m;
+        m = (hi < m) ? hi : m;
+    }
+    return (m < 0.0) ? 0.0 : m;
+}
+
+template <typename R>
+__device__ __forceinline__ CellRec<R> load_cell(const GridView &g, int32_t i)
+{
+    return reinterpret_cast<const CellRec<R> *>(g.cells)[i];
+}
+
+template <typename R>
+__device__ __forceinline__ CellAux<R> load_aux(const GridView &g, int32_t i)
+{
+    return reinterpret_cast<const CellAux<R> *>(g.aux)[i];
+}
+
+__device__ __forceinline__ int bin_of(double x, double lo, double hi, int n)
+{
+    if (x < lo) return 0;
+    const double t = (x - lo) / (hi - lo) * n;
+    if (t >= n) return n + 1;
+    return 1 + (int)t;
+}
+
+// Per-lane event counters, flushed to the job's spread counter slots.
+struct LaneCounters {
+    uint32_t v[10];
+};
+
+enum { C_EMITTED = 0, C_ESCAPED, C_ABSORBED, C_SCAT_HI, C_SCAT_DUST, C_CROSSINGS, C_PEELS,
+       C_UPAR_TRIES, C_PEEL_CROSSINGS, C_CAPPED };
+
+__device__ __forceinline__ void flush_counters(const JobView *J, LaneCounters &lc, int slot)
+{
+    unsigned long long *dst = J->counters + (size_t)slot * kNumCounters;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        if (lc.v[i]) atomicAdd(dst + i, (unsigned long long)lc.v[i]);
+        lc.v[i] = 0;
+    }
+}
+
+template <typename R>
+struct Photon {
+    double r[3];
+    double k[3];      // direction (double copy for geometry)
+    double ik[3];     // 1 / k
+    R kr[3];          // direction in the bulk precision
+    R x;              // lab-frame frequency (Doppler widths at 1e4 K)
+    double tau;       // optical depth left to the next interaction
+    CellBox c;
+    uint64_t id;
+    uint64_t events;
+    int32_t nscat;
+    int32_t status;   // 0 alive, 1 escaped, 2 absorbed, 3 capped
+    Rng<R> rng;
+};
+
+template <typename R>
+__device__ __forceinline__ void set_dir(Photon<R> &p, R kx, R ky, R kz)
+{
+    p.kr[0] = kx; p.kr[1] = ky; p.kr[2] = kz;
+    p.k[0] = (double)kx; p.k[1] = (double)ky; p.k[2] = (double)kz;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p.ik[d] = (p.k[d] != 0.0) ? 1.0 / p.k[d] : 0.0;
+}
+
+template <typename R>
+__device__ __forceinline__ void isotropic_dir(Photon<R> &p)
+{
+    using F = Fn<R>;
+    const R mu = R(2) * p.rng.next() - R(1);
+    const R Rphi = p.rng.next();
+    R c, s;
+    F::cossin2pi(Rphi, c, s);
+    const R st = F::sqrt(R(1) - mu * mu);
+    set_dir(p, st * c, st * s, mu);
+}
+
+// Optical depth along camera direction d (inverse id) from r in cell c to the
+// domain edge for lab frequency xl; negative once above the cut-off.
+template <typename R>
+__device__ double peel_tau(const JobView &J, CellBox c, const double r0[3], const double d[3],
+                           const double id[3], R xl, const R dr[3], LaneCounters &lc)
+{
+    double r[3] = {r0[0], r0[1], r0[2]};
+    double tau = 0.0;
+    for (;;) {
+        int axis;
+        bool by_sphere;
+        const double l = exit_distance(J.g, c, r, d, id, axis, by_sphere);
+        const CellRec<R> cr = load_cell<R>(J.g, c.cell);
+        const R xloc = xl * cr.s - (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz);
+        const R kt = cr.k0 * voigt_H<R>(cr.a, xloc) + cr.kd;
+        tau += (double)kt * l;
+        ++lc.v[C_PEEL_CROSSINGS];
+        if (tau > J.tau_peel_max) return -1.0;
+        if (by_sphere) return tau;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) r[e] += l * d[e];
+        if (!cross(J.g, c, r, d, axis)) return tau;
+    }
+}
+
+// What an event contributes toward camera direction d: comoving frequency
+// base + d.ua + g (k.d - 1) and phase weight (1 + rW (k.d)^2) / (1 + rW/3).
+// Emission: base = x_nat, ua = atom velocity; dust: base = x, ua = 0; H I:
+// base = x - u_par, ua = atom velocity, with recoil g and the event's rW.
+template <typename R>
+struct PeelSource {
+    R base, grec, rW;
+    R ua[3];
+};
+
+// One next-event contribution per camera from an event at p.r in cell p.c
+// (Sec. 6.1, eq. SB): W exp(-tau_esc) into the camera spectrum and image.
+template <typename R>
+__device__ void peel_off(const JobView &J, const Photon<R> &p, const CellRec<R> &cr,
+                         const PeelSource<R> &ps, LaneCounters &lc)
+{
+    using F = Fn<R>;
+    const R wn = R(1) + F::div(ps.rW, R(3));
+    for (int i = 0; i < J.n_cams; ++i) {
+        const double *cam = J.cam + 12 * i;
+        const double d[3] = {cam[0], cam[1], cam[2]};
+        const double id[3] = {cam[3], cam[4], cam[5]};
+        const R dr[3] = {(R)cam[0], (R)cam[1], (R)cam[2]};
+        const R muc = p.kr[0] * dr[0] + p.kr[1] * dr[1] + p.kr[2] * dr[2];
+        const R W = F::div(R(1) + ps.rW * muc * muc, wn);
+        const R xc = ps.base + (dr[0] * ps.ua[0] + dr[1] * ps.ua[1] + dr[2] * ps.ua[2]) +
+                     ps.grec * (muc - R(1));
+        const R xl = F::div(xc + (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz), cr.s);
+        ++lc.v[C_PEELS];
+        const double tau = peel_tau<R>(J, p.c, p.r, d, id, xl, dr, lc);
+        if (tau < 0.0) continue;
+        const double w = (double)W * ::exp(-tau);
+        if (J.record) J.rec_peel[p.id * J.n_cams + i] += w;
+        const int b = bin_of((double)xl, J.cam_xmin, J.cam_xmax, J.cam_nbins);
+        if (b >= 1 && b <= J.cam_nbins)
+            atomicAdd(J.cam_spec + (size_t)i * J.cam_nbins + (b - 1), w);
+        if (J.npix <= 0) continue;
+        double pu = 0.0, pv = 0.0;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const double rc = p.r[e] - J.g.centre[e];
+            pu += rc * cam[6 + e];
+            pv += rc * cam[9 + e];
+        }
+        pu = pu / J.fov + 0.5;
+        pv = pv / J.fov + 0.5;
+        if (pu >= 0.0 && pu < 1.0 && pv >= 0.0 && pv < 1.0) {
+            int iu = (int)(pu * J.npix), iv = (int)(pv * J.npix);
+            iu = (iu >= J.npix) ? J.npix - 1 : iu;
+            iv = (iv >= J.npix) ? J.npix - 1 : iv;
+            atomicAdd(J.cam_img + ((size_t)i * J.npix + iv) * J.npix + iu, w);
+        }
+    }
+}
+
+// Emission (Sec. 3.1.1): source position, isotropic direction, frequency,
+// first optical depth; draw order [source][blob offset] mu phi [x_nat, atom
+// velocity] tau.
+template <typename R>
+__device__ void emit(const JobView &J, Photon<R> &p, uint64_t id, LaneCounters &lc)
+{
+    using F = Fn<R>;
+    p.id = id;
+    p.events = 0;
+    p.nscat = 0;
+    p.status = 0;
+    p.rng.init(J.seed, id);
+    int src = 0;
+    if (J.n_src > 1) {
+        const double Rs = (double)p.rng.next();
+        while (src < J.n_src - 1 && Rs > J.src_cdf[src]) ++src;
+    }
+    p.r[0] = J.src_pos[3 * src];
+    p.r[1] = J.src_pos[3 * src + 1];
+    p.r[2] = J.src_pos[3 * src + 2];
+    if (J.src_kind == 1) {
+        const R R1 = p.rng.next(), R2 = p.rng.next(), R3 = p.rng.next(), R4 = p.rng.next();
+        const R q1 = F::sqrt(R(-2) * F::log(R1)), q2 = F::sqrt(R(-2) * F::log(R3));
+        R c2, s2, c4, s4;
+        F::cossin2pi(R2, c2, s2);
+        F::cossin2pi(R4, c4, s4);
+        p.r[0] += J.sigma * (double)(q1 * c2);
+        p.r[1] += J.sigma * (double)(q1 * s2);
+        p.r[2] += J.sigma * (double)(q2 * c4);
+    }
+    isotropic_dir(p);
+    ++lc.v[C_EMITTED];
+    p.x = R(0);
+    if (!locate(J.g, p.r, p.k, p.c)) {        // born outside the domain
+        p.status = 1;
+        return;
+    }
+    const CellRec<R> cr = load_cell<R>(J.g, p.c.cell);
+    R x = R(0);
+    R ua[3] = {R(0), R(0), R(0)};
+    R xnat = R(0);
+    if (J.freq_mode == 1) {                    // eq. init_freq
+        const R Rl = p.rng.next();
+        if constexpr (sizeof(R) == 8) {
+            xnat = cr.a * ::tan(kPi * (Rl - 0.5));
+        } else {
+            float c, s;
+            F::cossin2pi(0.5f * Rl, c, s);
+            xnat = -cr.a * F::div(c, s);
+        }
+        const R R1 = p.rng.next(), R2 = p.rng.next(), R3 = p.rng.next(), R4 = p.rng.next();
+        const R q1 = F::sqrt(-F::log(R1)), q2 = F::sqrt(-F::log(R3));
+        R c2, s2, c4, s4;
+        F::cossin2pi(R2, c2, s2);
+        F::cossin2pi(R4, c4, s4);
+        ua[0] = q1 * c2;
+        ua[1] = q1 * s2;
+        ua[2] = q2 * c4;
+        x = xnat + (p.kr[0] * ua[0] + p.kr[1] * ua[1] + p.kr[2] * ua[2]);
+    }
+    p.x = F::div(x + (p.kr[0] * cr.ux + p.kr[1] * cr.uy + p.kr[2] * cr.uz), cr.s);
+    if (J.n_cams > 0) {
+        const PeelSource<R> ps = {xnat, R(0), R(0), {ua[0], ua[1], ua[2]}};
+        peel_off<R>(J, p, cr, ps, lc);
+    }
+    p.tau = -(double)F::log(p.rng.next());
+}
+
+// Advances a live photon by one interaction (or to escape): march through
+// cells until the optical depth is spent, then scatter on H I or dust.
+template <typename R>
+__device__ void step(const JobView &J, Photon<R> &p, LaneCounters &lc)
+{
+    using F = Fn<R>;
+    CellRec<R> cr;
+    R xloc;
+    double ktot;
+    for (;;) {
+        cr = load_cell<R>(J.g, p.c.cell);
+        xloc = p.x * cr.s - (p.kr[0] * cr.ux + p.kr[1] * cr.uy + p.kr[2] * cr.uz);
+        int axis;
+        bool by_sphere;
+        const double l_exit = exit_distance(J.g, p.c, p.r, p.k, p.ik, axis, by_sphere);
+        const R kHI = cr.k0 * voigt_H<R>(cr.a, xloc);
+        ktot = (double)(kHI + cr.kd);
+        const double tau_cell = ktot * l_exit;
+        if (p.tau > tau_cell) {
+            p.tau -= tau_cell;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) p.r[d] += l_exit * p.k[d];
+            ++lc.v[C_CROSSINGS];
+            if (++p.events >= J.max_events) { p.status = 3; return; }
+            if (by_sphere || !cross(J.g, p.c, p.r, p.k, axis)) { p.status = 1; return; }
+            continue;
+        }
+        const double l = p.tau / ktot;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) p.r[d] += l * p.k[d];
+        break;
+    }
+    if (++p.events >= J.max_events || !(p.r[0] == p.r[0])) { p.status = 3; return; }
+
+    if (cr.kd > R(0) && p.rng.next() < F::div(cr.kd, (R)ktot)) {
+        if (p.rng.next() >= (R)J.g.albedo) { p.status = 2; return; }
+        isotropic_dir(p);                      // grey isotropic dust scattering
+        p.x = F::div(xloc + (p.kr[0] * cr.ux + p.kr[1] * cr.uy + p.kr[2] * cr.uz), cr.s);
+        ++lc.v[C_SCAT_DUST];
+        if (J.n_cams > 0) {
+            const PeelSource<R> ps = {xloc, R(0), R(0), {R(0), R(0), R(0)}};
+            peel_off<R>(J, p, cr, ps, lc);
+        }
+        p.tau = -(double)F::log(p.rng.next());
+        return;
+    }
+
+    // H I scattering (Sec. 3.1.3, 3.2.3, 3.2.4)
+    const R a = cr.a, xcw = cr.xcw;
+    uint32_t tries = 0;
+    const R upar = draw_upar<R>(a, xloc, xcw, p.rng, tries);
+    lc.v[C_UPAR_TRIES] += tries;
+    R xc = R(0);
+    if (J.xcrit_mode == 1) {
+        xc = (R)J.xcrit_global;
+    } else if (J.xcrit_mode == 2) {
+        const CellAux<R> ax = load_aux<R>(J.g, p.c.cell);
+        const R atau = a * cr.k0 * (R)min_face_distance(p.c, p.r) + ax.atau_nl;
+        xc = xcrit_of<R>(atau);
+    }
+    const R axl = (xloc < R(0)) ? -xloc : xloc;
+    if (axl >= xcw) xc = R(0);                 // already in the wing: no cut-off
+    R u1, u2;
+    draw_uperp<R>(xc, p.rng, u1, u2);
+    R e1[3], e2[3];
+    perp_basis<R>(p.kr, e1, e2);
+    R ua[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ua[d] = upar * p.kr[d] + u1 * e1[d] + u2 * e2[d];
+    const R rW = J.isotropic ? R(0) : ((axl < xcw) ? R(3.0 / 11.0) : R(1));
+    const R mu = draw_mu<R>(rW, p.rng);
+    R cph, sph;
+    F::cossin2pi(p.rng.next(), cph, sph);
+    const R st = F::sqrt(R(1) - mu * mu);
+    R kf[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) kf[d] = mu * p.kr[d] + st * (cph * e1[d] + sph * e2[d]);
+    const R nk = F::sqrt(kf[0] * kf[0] + kf[1] * kf[1] + kf[2] * kf[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) kf[d] = F::div(kf[d], nk);
+    R grec = R(0);
+    if (J.recoil) grec = load_aux<R>(J.g, p.c.cell).g;
+    const R xf = xloc - upar + (kf[0] * ua[0] + kf[1] * ua[1] + kf[2] * ua[2]) +
+                 grec * (mu - R(1));              // eq. x_f
+    ++p.nscat;
+    ++lc.v[C_SCAT_HI];
+    if (J.n_cams > 0) {
+        const PeelSource<R> ps = {xloc - upar, grec, rW, {ua[0], ua[1], ua[2]}};
+        peel_off<R>(J, p, cr, ps, lc);
+    }
+    set_dir(p, kf[0], kf[1], kf[2]);
+    p.x = F::div(xf + (kf[0] * cr.ux + kf[1] * cr.uy + kf[2] * cr.uz), cr.s);
+    p.tau = -(double)F::log(p.rng.next());
+}
+
+template <typename R>
+__device__ void finish(const JobView &J, const Photon<R> &p, LaneCounters &lc)
+{
+    if (p.status == 1) {
+        ++lc.v[C_ESCAPED];
+        if (J.n_bins > 0) {
+            const int b = bin_of((double)p.x, J.x_min, J.x_max, J.n_bins);
+            atomicAdd(J.spectrum + b, 1ull);
+        }
+    } else if (p.status == 2) {
+        ++lc.v[C_ABSORBED];
+    } else {
+        ++lc.v[C_CAPPED];
+    }
+    if (J.record) {
+        J.rec_x[p.id] = (double)p.x;
+        J.rec_nscat[p.id] = p.nscat;
+        J.rec_status[p.id] = p.status;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) J.rec_pos[3 * p.id + d] = J.box_min_cm[d] + p.r[d] * J.dx_cm;
+    }
+}
+
+__device__ __forceinline__ int find_job(const LaunchView &L, uint64_t g)
+{
+    int lo = 0, hi = L.n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.prefix[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Persistent photon pool.  Every lane runs photons until the shared queue is
+// drained; idle lanes of a wave are refilled together with one atomic.
+template <typename R>
+__global__ __launch_bounds__(256) void k_transport(LaunchView L)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kCounterSlots - 1));
+    Photon<R> p;
+    LaneCounters lc;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) lc.v[i] = 0;
+    const JobView *J = nullptr;
+    bool have = false, drained = false;
+    for (;;) {
+        if (!drained) {
+            const uint64_t need = __ballot(!have);
+            if (need) {
+                const int n_need = __popcll(need);
+                const int leader = __ffsll((unsigned long long)need) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(L.queue, (unsigned long long)n_need);
+                const uint32_t blo = __shfl((uint32_t)base, leader);
+                const uint32_t bhi = __shfl((uint32_t)(base >> 32), leader);
+                base = ((unsigned long long)bhi << 32) | blo;
+                if (base + n_need >= L.total) drained = true;
+                if (!have) {
+                    const uint64_t g = base + __popcll(need & lane_lt);
+                    if (g < L.total) {
+                        const int j = find_job(L, g);
+                        const JobView *Jn = &L.jobs[j];
+                        if (Jn != J) {
+                            if (J) flush_counters(J, lc, slot);
+                            J = Jn;
+                        }
+                        emit<R>(*J, p, L.first_id[j] + (g - L.prefix[j]), lc);
+                        have = true;
+                        if (p.status != 0) { finish<R>(*J, p, lc); have = false; }
+                    }
+                }
+            }
+        }
+        if (!__any(have)) {
+            if (drained) break;
+            continue;          // lanes were refilled with photons born outside
+        }
+        if (have) {
+            step<R>(*J, p, lc);
+            if (p.status != 0) {
+                finish<R>(*J, p, lc);
+                have = false;
+                if (lc.v[C_SCAT_HI] > (1u << 30) || lc.v[C_UPAR_TRIES] > (1u << 30) ||
+                    lc.v[C_PEEL_CROSSINGS] > (1u << 30) || lc.v[C_CROSSINGS] > (1u << 30))
+                    flush_counters(J, lc, slot);
+            }
+        }
+    }
+    if (J) flush_counters(J, lc, slot);
+}
+
+// ---------------------------------------------------------------------------
+// Device checks.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_voigt(int64_t n, const double *a, const double *x, double *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)voigt_H<R>((R)a[i], (R)x[i]);
+}
+
+template <typename R>
+__global__ void k_sample(int what, double p0, double p1, double p2, uint64_t seed, int64_t n,
+                         double *out, int32_t *draws)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Rng<R> rng;
+    rng.init(seed, (uint64_t)i);
+    if (what == 0) {
+        uint32_t tries = 0;
+        out[i] = (double)draw_upar<R>((R)p0, (R)p1, (R)p2, rng, tries);
+        draws[i] = (int32_t)rng.k;
+    } else if (what == 1) {
+        R u1, u2;
+        draw_uperp<R>((R)p0, rng, u1, u2);
+        out[2 * i] = (double)u1;
+        out[2 * i + 1] = (double)u2;
+    } else if (what == 2) {
+        out[i] = (double)draw_mu<R>((R)p0, rng);
+    } else {
+        const int64_t m = (int64_t)p0;
+        for (int64_t j = 0; j < m; ++j) out[i * m + j] = (double)rng.next();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_cell_setup(int64_t n, const double *n_HI, const double *T, const double *v,
+                             const double *k_dust, const double *atau_nl, double dx_cm,
+                             void *rd, void *ad, void *rf, void *af, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    const int64_t grid = (n + block - 1) / block;
+    hipLaunchKernelGGL(k_cell_setup, dim3((unsigned)grid), dim3(block), 0, s, n, n_HI, T, v,
+                       k_dust, atau_nl, dx_cm, (CellRec<double> *)rd, (CellAux<double> *)ad,
+                       (CellRec<float> *)rf, (CellAux<float> *)af);
+    return hipGetLastError();
+}
+
+hipError_t launch_transport(int precision, const LaunchView &L, int grid, int block,
+                            hipStream_t s)
+{
+    if (precision == 0)
+        hipLaunchKernelGGL(k_transport<double>, dim3(grid), dim3(block), 0, s, L);
+    else
+        hipLaunchKernelGGL(k_transport<float>, dim3(grid), dim3(block), 0, s, L);
+    return hipGetLastError();
+}
+
+hipError_t transport_occupancy(int precision, int block, int *blocks_per_cu)
+{
+    if (precision == 0)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_transport<double>,
+                                                            block, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_transport<float>,
+                                                        block, 0);
+}
+
+hipError_t launch_voigt(int precision, int64_t n, const double *a, const double *x, double *out,
+                        hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    const unsigned grid = (unsigned)((n + block - 1) / block);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_voigt<double>, dim3(grid), dim3(block), 0, s, n, a, x, out);
+    else
+        hipLaunchKernelGGL(k_voigt<float>, dim3(grid), dim3(block), 0, s, n, a, x, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(int precision, int what, double p0, double p1, double p2,
+                         uint64_t seed, int64_t n, double *out, int32_t *draws, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    const unsigned grid = (unsigned)((n + block - 1) / block);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_sample<double>, dim3(grid), dim3(block), 0, s, what, p0, p1, p2,
+                           seed, n, out, draws);
+    else
+        hipLaunchKernelGGL(k_sample<float>, dim3(grid), dim3(block), 0, s, what, p0, p1, p2,
+                           seed, n, out, draws);
+    return hipGetLastError();
+}
+
+}  // namespace colt

@@ -1,0 +1,22 @@
+// Host-side launchers of the transport kernels (defined in colt_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "colt_internal.h"
+
+namespace colt {
+
+hipError_t launch_cell_setup(int64_t n, const double *n_HI, const double *T, const double *v,
+                             const double *k_dust, const double *atau_nl, double dx_cm,
+                             void *rd, void *ad, void *rf, void *af, hipStream_t s);
+hipError_t launch_transport(int precision, const LaunchView &L, int grid, int block,
+                            hipStream_t s);
+hipError_t transport_occupancy(int precision, int block, int *blocks_per_cu);
+hipError_t launch_voigt(int precision, int64_t n, const double *a, const double *x, double *out,
+                        hipStream_t s);
+hipError_t launch_sample(int precision, int what, double p0, double p1, double p2,
+                         uint64_t seed, int64_t n, double *out, int32_t *draws, hipStream_t s);
+
+}  // namespace colt
