@@ -225,10 +225,13 @@ colt_status colt_eval_voigt(int32_t precision, const double *a, const double *x,
 
 /* Draws n samples of one sampler on the device; sample i uses photon stream
  * (seed, i) from its first draw, exactly as in transport.
- *   what 0: u_par for (a = p0, x = p1, x_cw = p2)   out[n], draws[n] uniforms used
+ *   what 0: u_par for (a = p0, x = p1, x_cw = p2) with the wave-cooperative
+ *           sampler used in transport      out[n], draws[n] = draw index after
  *   what 1: u_perp pair with cut-off p0              out[2n]
  *   what 2: mu for W ~ 1 + p0 mu^2                    out[n]
- *   what 3: uniform numbers (k = 0 .. p0-1 of stream i) out[n*p0] */
+ *   what 3: uniform numbers (k = 0 .. p0-1 of stream i) out[n*p0]
+ *   what 4: as 0 with x_i = p1 + 0.41 (i mod 23) (-1)^i (mixed requests in a wave)
+ *   what 5: as 0 with the one-lane sequential sampler */
 colt_status colt_sample(int32_t what, int32_t precision, double p0, double p1, double p2,
                         uint64_t seed, int64_t n, double *out, int32_t *draws, void *stream);
 

@@ -86,6 +86,9 @@ def lib():
         L.orc_cell_constants.restype = None
         L.orc_sample_upar.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_uint64, ctypes.c_int64, _dp, _ip]
+        L.orc_sample_upar_one.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_uint64, ctypes.c_uint64, _ip]
+        L.orc_sample_upar_one.restype = ctypes.c_double
         L.orc_sample_uperp.argtypes = [ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
         L.orc_sample_mu.argtypes = [ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
         L.orc_upar_split.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
@@ -140,6 +143,16 @@ def sample_upar(a, x, n, seed, xcw_val=None):
     draws = np.zeros(n, np.int32)
     lib().orc_sample_upar(a, x, xcw_val, seed, n, _ptr(out), _ptr(draws, _ip))
     return out, draws
+
+
+def sample_upar_one(a, x, seed, photon, xcw_val=None):
+    """u_par of one photon stream (seed, photon) from its first draw, and the
+    draw index after it."""
+    if xcw_val is None:
+        xcw_val = xcw(a)
+    d = ctypes.c_int32()
+    u = lib().orc_sample_upar_one(a, x, xcw_val, seed, photon, ctypes.byref(d))
+    return u, d.value
 
 
 def upar_split(a, x, xcw_val=None):

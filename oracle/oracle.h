@@ -110,6 +110,8 @@ void   orc_cell_constants(double T, double n_HI, double *a, double *sigma0, doub
  * each writes n samples and the number of uniforms consumed per sample. */
 void orc_sample_upar(double a, double x, double xcw, uint64_t seed, int64_t n,
                      double *out, int32_t *draws);
+double orc_sample_upar_one(double a, double x, double xcw, uint64_t seed, uint64_t photon,
+                           int32_t *draws);
 void orc_sample_uperp(double xcrit_eff, uint64_t seed, int64_t n, double *out2);
 void orc_sample_mu(double rW, uint64_t seed, int64_t n, double *out);
 double orc_upar_split(double a, double x, double xcw, double *u0);

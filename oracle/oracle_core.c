@@ -136,11 +136,16 @@ double orc_upar_split(double a, double X, double xcw, double *u0_out)
     return p;
 }
 
+/* Draw layout: the sampler starts on a fresh counter block (an even draw
+ * index); each candidate of the |x| <= 1 proposal takes one block (two
+ * draws), each candidate of the two-part proposal two blocks (three draws
+ * used, the fourth left unused), the |x| >= 9 Gaussian one block. */
 double orc_draw_upar(double a, double x, double xcw, orc_stream *s, int64_t *tries)
 {
     double sgn = (x < 0.0) ? -1.0 : 1.0;
     double X = fabs(x);
     double u;
+    s->k = (s->k + 1) & ~(uint64_t)1;
     if (X <= 1.0) {
         for (;;) {
             double theta = ORC_PI * (orc_draw(s) - 0.5);
@@ -167,6 +172,7 @@ double orc_draw_upar(double a, double x, double xcw, orc_stream *s, int64_t *tri
                 accept = exp(u0 * u0 - u * u);
             }
             double Racc = orc_draw(s);
+            s->k += 1;                                       /* unused fourth draw */
             ++*tries;
             if (Racc < accept) break;
         }
@@ -233,6 +239,16 @@ void orc_sample_upar(double a, double x, double xcw, uint64_t seed, int64_t n,
         out[i] = orc_draw_upar(a, x, xcw, &s, &tries);
         if (draws) draws[i] = (int32_t)s.k;
     }
+}
+
+double orc_sample_upar_one(double a, double x, double xcw, uint64_t seed, uint64_t photon,
+                           int32_t *draws)
+{
+    orc_stream s = { seed, photon, 0 };
+    int64_t tries = 0;
+    double u = orc_draw_upar(a, x, xcw, &s, &tries);
+    if (draws) *draws = (int32_t)s.k;
+    return u;
 }
 
 void orc_sample_uperp(double xcrit_eff, uint64_t seed, int64_t n, double *out2)

@@ -562,6 +562,7 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
         std::vector<JobView> views;
         std::vector<uint64_t> prefix(1, 0), first;
         std::vector<colt_job> members;
+        bool cams = false;
         for (int i = 0; i < n_jobs; ++i) {
             colt_job j = jobs[i];
             if (j->params.precision != prec) continue;
@@ -569,6 +570,7 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
             const uint64_t take = (quota && quota < left) ? quota : left;
             if (take == 0) continue;
             views.push_back(j->view);
+            cams = cams || j->params.n_cams > 0;
             first.push_back(j->launched);
             prefix.push_back(prefix.back() + take);
             members.push_back(j);
@@ -597,7 +599,7 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
         L.total = prefix.back();
         int per_cu = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 0;
         if (per_cu <= 0) {
-            HIP_TRY(transport_occupancy(prec, block, &per_cu));
+            HIP_TRY(transport_occupancy(prec, cams, nj == 1, block, &per_cu));
             if (per_cu <= 0) per_cu = 1;
         }
         const uint64_t lanes_needed = (L.total + 63) / 64 * 64;
@@ -612,7 +614,7 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
             }
             HIP_TRY(hipEventRecord(g_t0, s));
         }
-        HIP_TRY(launch_transport(prec, L, (int)grid, block, s));
+        HIP_TRY(launch_transport(prec, cams, L, (int)grid, block, s));
         if (timed) {
             HIP_TRY(hipEventRecord(g_t1, s));
             g_timed = true;
@@ -708,7 +710,8 @@ colt_status colt_eval_voigt(int32_t precision, const double *a, const double *x,
 colt_status colt_sample(int32_t what, int32_t precision, double p0, double p1, double p2,
                         uint64_t seed, int64_t n, double *out, int32_t *draws, void *stream)
 {
-    if (what < 0 || what > 3 || n < 0 || (n > 0 && !out) || (what == 0 && n > 0 && !draws))
+    const bool upar = what == 0 || what == 4 || what == 5;
+    if (what < 0 || what > 5 || n < 0 || (n > 0 && !out) || (upar && n > 0 && !draws))
         return fail(COLT_ERR_ARG, "bad sampler request");
     if (precision != 0 && precision != 1) return fail(COLT_ERR_ARG, "precision 0 or 1");
     if (what == 3 && !(p0 >= 1.0 && p0 <= 4096.0)) return fail(COLT_ERR_ARG, "1..4096 draws");
@@ -721,7 +724,7 @@ colt_status colt_sample(int32_t what, int32_t precision, double p0, double p1, d
     hipError_t e = hipMalloc(&dd, n * sizeof(int32_t));
     if (e == hipSuccess) e = launch_sample(precision, what, p0, p1, p2, seed, n, d, dd, s);
     if (e == hipSuccess) e = hipMemcpyAsync(out, d, n * per * 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && what == 0)
+    if (e == hipSuccess && upar)
         e = hipMemcpyAsync(draws, dd, n * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(d);

@@ -35,67 +35,99 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32
     }
 }
 
-// Per-photon stream: uniform k of photon `id` under key `seed` uses counter
-// block (k / per_block) of the photon's counter space.  FP64 takes 53 bits
-// from a word pair (two draws per block); FP32 takes one word per draw (four
-// per block).  The last block's unused words are cached in registers.
+// Per-photon stream: uniform k of photon `id` under key `seed` comes from
+// counter block (k / per_block) of the photon's counter space.  FP64 takes 53
+// bits from a word pair (two draws per block); FP32 takes one word per draw
+// (four per block).  The last block's unused words are cached in registers.
+// The u_par sampler starts on a fresh block and addresses its blocks directly.
+__device__ __forceinline__ double u53(uint32_t lo, uint32_t hi)
+{
+    const uint64_t m = ((((uint64_t)hi) << 32) | lo) >> 11;
+    return ((double)m + 1.0) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ float u32f(uint32_t w)
+{
+    // (0, 1]: w 2^-32 + 2^-33, rounded to float
+    return __builtin_fmaf((float)w, 0x1.0p-32f, 0x1.0p-33f);
+}
+
+struct RngKey {
+    uint32_t key0, key1, id0, id1;
+    __device__ __forceinline__ void block(uint64_t b, uint32_t &w0, uint32_t &w1, uint32_t &w2,
+                                          uint32_t &w3) const
+    {
+        uint32_t c0 = (uint32_t)b, c1 = (uint32_t)(b >> 32), c2 = id0, c3 = id1;
+        philox4x32_10(c0, c1, c2, c3, key0, key1);
+        w0 = c0; w1 = c1; w2 = c2; w3 = c3;
+    }
+};
+
 template <typename R>
 struct Rng;
 
 template <>
 struct Rng<double> {
-    uint32_t key0, key1, id0, id1;
+    static constexpr int kPerBlock = 2;
+    RngKey key;
     uint64_t k;
     uint32_t w2, w3;
     __device__ void init(uint64_t seed, uint64_t id)
     {
-        key0 = (uint32_t)seed; key1 = (uint32_t)(seed >> 32);
-        id0 = (uint32_t)id; id1 = (uint32_t)(id >> 32);
+        key.key0 = (uint32_t)seed; key.key1 = (uint32_t)(seed >> 32);
+        key.id0 = (uint32_t)id; key.id1 = (uint32_t)(id >> 32);
         k = 0;
     }
     __device__ __forceinline__ double next()
     {
         uint32_t lo, hi;
         if ((k & 1) == 0) {
-            const uint64_t b = k >> 1;
-            uint32_t c0 = (uint32_t)b, c1 = (uint32_t)(b >> 32), c2 = id0, c3 = id1;
-            philox4x32_10(c0, c1, c2, c3, key0, key1);
-            lo = c0; hi = c1; w2 = c2; w3 = c3;
+            key.block(k >> 1, lo, hi, w2, w3);
         } else {
             lo = w2; hi = w3;
         }
         ++k;
-        const uint64_t m = ((((uint64_t)hi) << 32) | lo) >> 11;
-        return ((double)m + 1.0) * 0x1.0p-53;
+        return u53(lo, hi);
+    }
+    // moves to the start of the next unused block; returns that block
+    __device__ __forceinline__ uint64_t align()
+    {
+        k = (k + 1) & ~(uint64_t)1;
+        return k >> 1;
     }
 };
 
 template <>
 struct Rng<float> {
-    uint32_t key0, key1, id0, id1;
+    static constexpr int kPerBlock = 4;
+    RngKey key;
     uint64_t k;
     uint32_t w1, w2, w3;
     __device__ void init(uint64_t seed, uint64_t id)
     {
-        key0 = (uint32_t)seed; key1 = (uint32_t)(seed >> 32);
-        id0 = (uint32_t)id; id1 = (uint32_t)(id >> 32);
+        key.key0 = (uint32_t)seed; key.key1 = (uint32_t)(seed >> 32);
+        key.id0 = (uint32_t)id; key.id1 = (uint32_t)(id >> 32);
         k = 0;
     }
+    // the unused words of the current block wait in w1, w2, w3 (oldest first);
+    // shifting them keeps every access static so the state stays in registers
     __device__ __forceinline__ float next()
     {
-        const uint32_t j = (uint32_t)k & 3u;
         uint32_t w;
-        if (j == 0) {
-            const uint64_t b = k >> 2;
-            uint32_t c0 = (uint32_t)b, c1 = (uint32_t)(b >> 32), c2 = id0, c3 = id1;
-            philox4x32_10(c0, c1, c2, c3, key0, key1);
-            w = c0; w1 = c1; w2 = c2; w3 = c3;
+        if (((uint32_t)k & 3u) == 0) {
+            key.block(k >> 2, w, w1, w2, w3);
         } else {
-            w = (j == 1) ? w1 : ((j == 2) ? w2 : w3);
+            w = w1;
+            w1 = w2;
+            w2 = w3;
         }
         ++k;
-        // (0, 1]: w 2^-32 + 2^-33, rounded to float
-        return __builtin_fmaf((float)w, 0x1.0p-32f, 0x1.0p-33f);
+        return u32f(w);
+    }
+    __device__ __forceinline__ uint64_t align()
+    {
+        k = (k + 3) & ~(uint64_t)3;
+        return k >> 2;
     }
 };
 
@@ -187,88 +219,160 @@ __device__ __forceinline__ R voigt_H(R a, R x)
 // (Sec. 3.2.3): Lorentzian proposal for |x| <= 1; two-part comparison
 // function split at u0 for 1 < |x| < 9 (u0,core below x_cw, u0,wing above),
 // redrawing the part after each rejection; Gaussian of mean 1/x for |x| >= 9.
-// Draw order: per attempt (theta, accept) or (part, theta, accept).
+//
+// Draw layout: the sampler starts on a fresh counter block B0.  Candidate t
+// uses block B0 + t (FP32: words part, theta, accept; FP64 |x| <= 1: theta,
+// accept) or blocks B0 + 2t, B0 + 2t + 1 (FP64 two-part: part, theta, accept
+// from the first three word pairs).  Because a candidate's draws depend only
+// on (photon, t), candidates can be evaluated in any order or in parallel and
+// the first accepted one in t-order is the sequential result.
+//
 // The FP64 form follows the paper's expressions literally; the FP32 form
 // evaluates the same quantities through phi = theta + pi/2, which keeps the
 // angles near -pi/2 accurate in single precision.
 // ---------------------------------------------------------------------------
+enum { UPAR_CORE = 0, UPAR_SPLIT = 1, UPAR_GAUSS = 2 };
+
 template <typename R>
-__device__ __forceinline__ R draw_upar(R a, R x, R xcw, Rng<R> &rng, uint32_t &tries)
+struct UparReq {
+    R X;          // |x|
+    R a;
+    R u0;         // split point (two-part regime)
+    R p;          // probability of the part below u0
+    R th0;        // FP64: theta0; FP32: phi0 = theta0 + pi/2
+    int regime;
+};
+
+template <typename R>
+__device__ __forceinline__ UparReq<R> upar_setup(R a, R x, R xcw)
 {
     using F = Fn<R>;
-    const R sgn = (x < R(0)) ? R(-1) : R(1);
-    const R X = (x < R(0)) ? -x : x;
-    R u;
-    if (X <= R(1)) {
-        for (;;) {
-            const R Rth = rng.next();
-            if constexpr (sizeof(R) == 8) {
-                u = a * F::tan(kPi * (Rth - 0.5)) + X;
-            } else {
-                // tan(pi (R - 1/2)) = -cos(pi R) / sin(pi R)
-                float c, s;
-                F::cossin2pi(0.5f * Rth, c, s);
-                u = X - a * F::div(c, s);
-            }
-            const R Racc = rng.next();
-            ++tries;
-            if (Racc < F::exp(-u * u)) break;
-        }
-    } else if (X < R(9)) {
+    UparReq<R> q;
+    q.X = (x < R(0)) ? -x : x;
+    q.a = a;
+    q.u0 = R(0);
+    q.p = R(0);
+    q.th0 = R(0);
+    q.regime = (q.X <= R(1)) ? UPAR_CORE : ((q.X < R(9)) ? UPAR_SPLIT : UPAR_GAUSS);
+    if (q.regime == UPAR_SPLIT) {
+        const R X = q.X;
         R u0;
         if (X < xcw)
             u0 = X - F::div(R(1), X + F::div(F::exp(R(1) - X * X), a));
         else
             u0 = xcw - F::div(R(1), xcw) + R(0.15) * (X - xcw);
         const R e0 = F::exp(-u0 * u0);
+        q.u0 = u0;
         if constexpr (sizeof(R) == 8) {
             const double theta0 = ::atan((u0 - X) / a);
-            const double p = (theta0 + kPi / 2.0) /
-                             ((1.0 - e0) * theta0 + (1.0 + e0) * kPi / 2.0);
-            for (;;) {
-                const double Rp = rng.next();
-                const double Rth = rng.next();
-                double acc;
-                if (Rp <= p) {
-                    const double theta = -kPi / 2.0 + Rth * (theta0 + kPi / 2.0);
-                    u = a * ::tan(theta) + X;
-                    acc = ::exp(-u * u);
-                } else {
-                    const double theta = theta0 + Rth * (kPi / 2.0 - theta0);
-                    u = a * ::tan(theta) + X;
-                    acc = ::exp(u0 * u0 - u * u);
-                }
-                const double Racc = rng.next();
-                ++tries;
-                if (Racc < acc) break;
-            }
+            q.th0 = theta0;
+            q.p = (theta0 + kPi / 2.0) / ((1.0 - e0) * theta0 + (1.0 + e0) * kPi / 2.0);
         } else {
-            // phi0 = theta0 + pi/2 = atan(a / (X - u0)), u0 < X
             const float phi0 = F::atan(F::div(a, X - u0));
-            const float p = F::div(phi0, phi0 + e0 * (float(kPi) - phi0));
-            const float u0sq = u0 * u0;
-            for (;;) {
-                const float Rp = rng.next();
-                const float Rth = rng.next();
-                // theta = phi - pi/2, a tan(theta) = -a cos(phi) / sin(phi)
-                const bool lower = Rp <= p;
-                const float phi = lower ? Rth * phi0 : phi0 + Rth * (float(kPi) - phi0);
-                float c, s;
-                F::cossin2pi(phi * float(0.5 / kPi), c, s);
-                u = X - a * F::div(c, s);
-                const float acc = lower ? F::exp(-u * u) : F::exp(u0sq - u * u);
-                const float Racc = rng.next();
-                ++tries;
-                if (Racc < acc) break;
-            }
+            q.th0 = phi0;
+            q.p = F::div(phi0, phi0 + e0 * (float(kPi) - phi0));
         }
-    } else {
-        const R R1 = rng.next();
-        const R R2 = rng.next();
-        R c, s;
-        F::cossin2pi(R2, c, s);
-        u = F::div(R(1), X) + F::sqrt(-F::log(R1)) * c;
     }
+    return q;
+}
+
+// Uniform draws per candidate in stream units (advance of the draw index).
+template <typename R>
+__device__ __forceinline__ uint32_t upar_stride(int regime)
+{
+    if constexpr (sizeof(R) == 8) return (regime == UPAR_SPLIT) ? 4u : 2u;
+    return 4u;
+}
+
+// Candidate t of request q (unsigned |u|) from the photon's blocks starting at B0.
+template <typename R>
+__device__ __forceinline__ bool upar_candidate(const UparReq<R> &q, const RngKey &key,
+                                               uint64_t B0, uint32_t t, R &u)
+{
+    using F = Fn<R>;
+    uint32_t w0, w1, w2, w3;
+    if constexpr (sizeof(R) == 8) {
+        if (q.regime == UPAR_CORE) {
+            key.block(B0 + t, w0, w1, w2, w3);
+            const double theta = kPi * (u53(w0, w1) - 0.5);
+            u = q.a * ::tan(theta) + q.X;
+            return u53(w2, w3) < ::exp(-u * u);
+        }
+        key.block(B0 + 2ull * t, w0, w1, w2, w3);
+        const double Rp = u53(w0, w1), Rth = u53(w2, w3);
+        key.block(B0 + 2ull * t + 1, w0, w1, w2, w3);
+        const double Racc = u53(w0, w1);
+        double acc;
+        if (Rp <= q.p) {
+            const double theta = -kPi / 2.0 + Rth * (q.th0 + kPi / 2.0);
+            u = q.a * ::tan(theta) + q.X;
+            acc = ::exp(-u * u);
+        } else {
+            const double theta = q.th0 + Rth * (kPi / 2.0 - q.th0);
+            u = q.a * ::tan(theta) + q.X;
+            acc = ::exp(q.u0 * q.u0 - u * u);
+        }
+        return Racc < acc;
+    } else {
+        key.block(B0 + t, w0, w1, w2, w3);
+        float phi, uacc_bias = 0.0f;
+        bool lower = true;
+        float Racc;
+        if (q.regime == UPAR_CORE) {
+            phi = float(kPi) * u32f(w0);          // theta = pi (R - 1/2)
+            Racc = u32f(w1);
+        } else {
+            lower = u32f(w0) <= q.p;
+            const float Rth = u32f(w1);
+            phi = lower ? Rth * q.th0 : q.th0 + Rth * (float(kPi) - q.th0);
+            Racc = u32f(w2);
+            if (!lower) uacc_bias = q.u0 * q.u0;
+        }
+        float c, s;
+        F::cossin2pi(phi * float(0.5 / kPi), c, s);
+        u = q.X - q.a * F::div(c, s);              // a tan(phi - pi/2) = -a cot(phi)
+        return Racc < F::exp(uacc_bias - u * u);
+    }
+}
+
+// |x| >= 9: Gaussian of mean 1/|x| (variance 1/2) from one block.
+template <typename R>
+__device__ __forceinline__ R upar_gauss(const UparReq<R> &q, const RngKey &key, uint64_t B0)
+{
+    using F = Fn<R>;
+    uint32_t w0, w1, w2, w3;
+    key.block(B0, w0, w1, w2, w3);
+    R R1, R2;
+    if constexpr (sizeof(R) == 8) {
+        R1 = u53(w0, w1);
+        R2 = u53(w2, w3);
+    } else {
+        R1 = u32f(w0);
+        R2 = u32f(w1);
+    }
+    R c, s;
+    F::cossin2pi(R2, c, s);
+    return F::div(R(1), q.X) + F::sqrt(-F::log(R1)) * c;
+}
+
+// Sequential sampler (one lane): signed u_par; advances the stream past the
+// accepted candidate and counts candidates in `tries`.
+template <typename R>
+__device__ __forceinline__ R draw_upar(R a, R x, R xcw, Rng<R> &rng, uint32_t &tries)
+{
+    const UparReq<R> q = upar_setup<R>(a, x, xcw);
+    const R sgn = (x < R(0)) ? R(-1) : R(1);
+    const uint64_t B0 = rng.align();
+    R u;
+    if (q.regime == UPAR_GAUSS) {
+        u = upar_gauss<R>(q, rng.key, B0);
+        rng.k += Rng<R>::kPerBlock;
+        return sgn * u;
+    }
+    uint32_t t = 0;
+    while (!upar_candidate<R>(q, rng.key, B0, t, u)) ++t;
+    tries += t + 1;
+    rng.k += (uint64_t)upar_stride<R>(q.regime) * (t + 1);
     return sgn * u;
 }
 

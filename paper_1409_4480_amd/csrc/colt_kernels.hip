@@ -82,7 +82,7 @@ __device__ __forceinline__ int side_of(double r, double mid, double k)
 
 // Finds the cell holding r for a photon moving along k; false if r is outside
 // the domain (box or escape sphere).
-__device__ bool locate(const GridView &g, const double r[3], const double k[3], CellBox &c)
+__device__ __forceinline__ bool locate(const GridView &g, const double r[3], const double k[3], CellBox &c)
 {
     int ib[3];
 #pragma unroll
@@ -166,19 +166,39 @@ __device__ __forceinline__ double exit_distance(const GridView &g, const CellBox
 }
 
 // Moves a photon on the exit face of `axis` into the next cell; false if it
-// leaves the domain.
+// leaves the domain.  The axis is selected with explicit branches so that the
+// position and cell arrays stay in registers.
+__device__ __forceinline__ void snap_face(CellBox &c, double r[3], const double k[3], int axis,
+                                          int &step)
+{
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (d == axis) {
+            step = (k[d] > 0.0) ? 1 : -1;
+            r[d] = (k[d] > 0.0) ? c.lo[d] + c.size : c.lo[d];
+        }
+    }
+}
+
 __device__ __forceinline__ bool cross(const GridView &g, CellBox &c, double r[3],
                                       const double k[3], int axis)
 {
-    r[axis] = (k[axis] > 0.0) ? c.lo[axis] + c.size : c.lo[axis];
+    int step = 0;
+    snap_face(c, r, k, axis, step);
     if (g.kind == 0) {
-        const int step = (k[axis] > 0.0) ? 1 : -1;
-        const int i = (int)c.lo[axis] + step;
-        if (i < 0 || i >= g.n[axis]) return false;
-        c.lo[axis] = (double)i;
-        const int stride = (axis == 0) ? 1 : ((axis == 1) ? g.n[0] : g.n[0] * g.n[1]);
-        c.cell += step * stride;
-        return true;
+        bool inside = true;
+        int stride = 1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (d == axis) {
+                const int i = (int)c.lo[d] + step;
+                inside = (i >= 0) && (i < g.n[d]);
+                c.lo[d] = (double)i;
+                c.cell += step * stride;
+            }
+            stride *= g.n[d];
+        }
+        return inside;
     }
     return locate(g, r, k, c);
 }
@@ -273,8 +293,9 @@ __device__ __forceinline__ void isotropic_dir(Photon<R> &p)
 // Optical depth along camera direction d (inverse id) from r in cell c to the
 // domain edge for lab frequency xl; negative once above the cut-off.
 template <typename R>
-__device__ double peel_tau(const JobView &J, CellBox c, const double r0[3], const double d[3],
-                           const double id[3], R xl, const R dr[3], LaneCounters &lc)
+__device__ __forceinline__ double peel_tau(const JobView &J, CellBox c, const double r0[3],
+                                           const double d[3], const double id[3], R xl,
+                                           const R dr[3], LaneCounters &lc)
 {
     double r[3] = {r0[0], r0[1], r0[2]};
     double tau = 0.0;
@@ -308,8 +329,9 @@ struct PeelSource {
 // One next-event contribution per camera from an event at p.r in cell p.c
 // (Sec. 6.1, eq. SB): W exp(-tau_esc) into the camera spectrum and image.
 template <typename R>
-__device__ void peel_off(const JobView &J, const Photon<R> &p, const CellRec<R> &cr,
-                         const PeelSource<R> &ps, LaneCounters &lc)
+__device__ __forceinline__ void peel_off(const JobView &J, const Photon<R> &p,
+                                         const CellRec<R> &cr, const PeelSource<R> &ps,
+                                         LaneCounters &lc)
 {
     using F = Fn<R>;
     const R wn = R(1) + F::div(ps.rW, R(3));
@@ -353,8 +375,9 @@ __device__ void peel_off(const JobView &J, const Photon<R> &p, const CellRec<R> 
 // Emission (Sec. 3.1.1): source position, isotropic direction, frequency,
 // first optical depth; draw order [source][blob offset] mu phi [x_nat, atom
 // velocity] tau.
-template <typename R>
-__device__ void emit(const JobView &J, Photon<R> &p, uint64_t id, LaneCounters &lc)
+template <typename R, bool CAMS>
+__device__ __forceinline__ void emit(const JobView &J, Photon<R> &p, uint64_t id,
+                                     LaneCounters &lc)
 {
     using F = Fn<R>;
     p.id = id;
@@ -411,22 +434,23 @@ __device__ void emit(const JobView &J, Photon<R> &p, uint64_t id, LaneCounters &
         x = xnat + (p.kr[0] * ua[0] + p.kr[1] * ua[1] + p.kr[2] * ua[2]);
     }
     p.x = F::div(x + (p.kr[0] * cr.ux + p.kr[1] * cr.uy + p.kr[2] * cr.uz), cr.s);
-    if (J.n_cams > 0) {
-        const PeelSource<R> ps = {xnat, R(0), R(0), {ua[0], ua[1], ua[2]}};
-        peel_off<R>(J, p, cr, ps, lc);
+    if constexpr (CAMS) {
+        if (J.n_cams > 0) {
+            const PeelSource<R> ps = {xnat, R(0), R(0), {ua[0], ua[1], ua[2]}};
+            peel_off<R>(J, p, cr, ps, lc);
+        }
     }
     p.tau = -(double)F::log(p.rng.next());
 }
 
-// Advances a live photon by one interaction (or to escape): march through
-// cells until the optical depth is spent, then scatter on H I or dust.
+// Ray tracing (Sec. 3.1.2): march cell by cell until the optical depth is
+// spent (returns true with the photon at the interaction point, the cell's
+// line data in cr, the comoving frequency in xloc and the total opacity in
+// ktot) or the photon leaves the domain / reaches the event cap (false).
 template <typename R>
-__device__ void step(const JobView &J, Photon<R> &p, LaneCounters &lc)
+__device__ __forceinline__ bool march(const JobView &J, Photon<R> &p, CellRec<R> &cr, R &xloc,
+                                      double &ktot, LaneCounters &lc)
 {
-    using F = Fn<R>;
-    CellRec<R> cr;
-    R xloc;
-    double ktot;
     for (;;) {
         cr = load_cell<R>(J.g, p.c.cell);
         xloc = p.x * cr.s - (p.kr[0] * cr.ux + p.kr[1] * cr.uy + p.kr[2] * cr.uz);
@@ -441,35 +465,54 @@ __device__ void step(const JobView &J, Photon<R> &p, LaneCounters &lc)
 #pragma unroll
             for (int d = 0; d < 3; ++d) p.r[d] += l_exit * p.k[d];
             ++lc.v[C_CROSSINGS];
-            if (++p.events >= J.max_events) { p.status = 3; return; }
-            if (by_sphere || !cross(J.g, p.c, p.r, p.k, axis)) { p.status = 1; return; }
+            if (++p.events >= J.max_events) { p.status = 3; return false; }
+            if (by_sphere || !cross(J.g, p.c, p.r, p.k, axis)) { p.status = 1; return false; }
             continue;
         }
         const double l = p.tau / ktot;
 #pragma unroll
         for (int d = 0; d < 3; ++d) p.r[d] += l * p.k[d];
-        break;
+        if (++p.events >= J.max_events || !(p.r[0] == p.r[0])) { p.status = 3; return false; }
+        return true;
     }
-    if (++p.events >= J.max_events || !(p.r[0] == p.r[0])) { p.status = 3; return; }
+}
 
+// Interaction channel: grey dust with probability k_dust / k_tot (absorbed
+// unless a second draw falls below the albedo, else isotropic scattering with
+// the comoving frequency kept); otherwise an H I scattering (returns true).
+template <typename R, bool CAMS>
+__device__ __forceinline__ bool interact(const JobView &J, Photon<R> &p, const CellRec<R> &cr,
+                                         R xloc, double ktot, LaneCounters &lc)
+{
+    using F = Fn<R>;
     if (cr.kd > R(0) && p.rng.next() < F::div(cr.kd, (R)ktot)) {
-        if (p.rng.next() >= (R)J.g.albedo) { p.status = 2; return; }
-        isotropic_dir(p);                      // grey isotropic dust scattering
+        if (p.rng.next() >= (R)J.g.albedo) { p.status = 2; return false; }
+        isotropic_dir(p);
         p.x = F::div(xloc + (p.kr[0] * cr.ux + p.kr[1] * cr.uy + p.kr[2] * cr.uz), cr.s);
         ++lc.v[C_SCAT_DUST];
-        if (J.n_cams > 0) {
-            const PeelSource<R> ps = {xloc, R(0), R(0), {R(0), R(0), R(0)}};
-            peel_off<R>(J, p, cr, ps, lc);
+        if constexpr (CAMS) {
+            if (J.n_cams > 0) {
+                const PeelSource<R> ps = {xloc, R(0), R(0), {R(0), R(0), R(0)}};
+                peel_off<R>(J, p, cr, ps, lc);
+            }
         }
         p.tau = -(double)F::log(p.rng.next());
-        return;
+        return false;
     }
+    return true;
+}
 
-    // H I scattering (Sec. 3.1.3, 3.2.3, 3.2.4)
+// H I scattering after the parallel velocity is known (Sec. 3.1.3, 3.2.4):
+// perpendicular velocity (truncated below x_crit when core-skipping applies),
+// new direction from the phase function, redistributed frequency (eq. x_f),
+// next-event tallies and the next optical depth.
+template <typename R, bool CAMS>
+__device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
+                                               const CellRec<R> &cr, R xloc, R upar,
+                                               LaneCounters &lc)
+{
+    using F = Fn<R>;
     const R a = cr.a, xcw = cr.xcw;
-    uint32_t tries = 0;
-    const R upar = draw_upar<R>(a, xloc, xcw, p.rng, tries);
-    lc.v[C_UPAR_TRIES] += tries;
     R xc = R(0);
     if (J.xcrit_mode == 1) {
         xc = (R)J.xcrit_global;
@@ -504,9 +547,11 @@ __device__ void step(const JobView &J, Photon<R> &p, LaneCounters &lc)
                  grec * (mu - R(1));              // eq. x_f
     ++p.nscat;
     ++lc.v[C_SCAT_HI];
-    if (J.n_cams > 0) {
-        const PeelSource<R> ps = {xloc - upar, grec, rW, {ua[0], ua[1], ua[2]}};
-        peel_off<R>(J, p, cr, ps, lc);
+    if constexpr (CAMS) {
+        if (J.n_cams > 0) {
+            const PeelSource<R> ps = {xloc - upar, grec, rW, {ua[0], ua[1], ua[2]}};
+            peel_off<R>(J, p, cr, ps, lc);
+        }
     }
     set_dir(p, kf[0], kf[1], kf[2]);
     p.x = F::div(xf + (kf[0] * cr.ux + kf[1] * cr.uy + kf[2] * cr.uz), cr.s);
@@ -514,7 +559,7 @@ __device__ void step(const JobView &J, Photon<R> &p, LaneCounters &lc)
 }
 
 template <typename R>
-__device__ void finish(const JobView &J, const Photon<R> &p, LaneCounters &lc)
+__device__ __forceinline__ void finish(const JobView &J, const Photon<R> &p, LaneCounters &lc)
 {
     if (p.status == 1) {
         ++lc.v[C_ESCAPED];
@@ -536,6 +581,99 @@ __device__ void finish(const JobView &J, const Photon<R> &p, LaneCounters &lc)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Cooperative u_par sampling.  The lanes of a wave that need a parallel atom
+// velocity (two-part or core proposal) post their requests in LDS; in each
+// round every lane of the wave evaluates one candidate: lane L works for the
+// (L mod m)-th open request (m open requests), on its candidate number
+// base + L / m.  The smallest accepted candidate number of a request is its
+// sequential result, so the outcome equals the one-lane loop exactly while
+// all 64 lanes stay busy until the last request of the wave is served.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct UparSlot {
+    R X, a, u0, p, th0;
+    int32_t regime;
+    uint32_t key0, key1, id0, id1, b0lo, b0hi;
+    uint32_t base;
+};
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr uint32_t kMaxUparRounds = 1u << 22;   // bound on rounds; never reached in practice
+
+// All 64 lanes of the wave must call this together.  On return, lanes with
+// `need` hold the unsigned |u_par| in u and the accepted candidate number in t
+// (ok = false only if the round bound was hit).
+template <typename R>
+__device__ __forceinline__ void coop_upar(bool need, const UparReq<R> &q, const RngKey &key,
+                                          uint64_t B0, R &u, uint32_t &t, bool &ok,
+                                          UparSlot<R> *slots, int32_t *table, uint32_t *first)
+{
+    const int lane = threadIdx.x & 63;
+    ok = true;
+    uint32_t base = 0;
+    if (need) {
+        UparSlot<R> s;
+        s.X = q.X; s.a = q.a; s.u0 = q.u0; s.p = q.p; s.th0 = q.th0; s.regime = q.regime;
+        s.key0 = key.key0; s.key1 = key.key1; s.id0 = key.id0; s.id1 = key.id1;
+        s.b0lo = (uint32_t)B0; s.b0hi = (uint32_t)(B0 >> 32);
+        s.base = 0;
+        slots[lane] = s;
+    }
+    for (uint32_t round = 0;; ++round) {
+        const uint64_t S = __ballot(need);
+        if (S == 0) break;
+        const int m = __popcll(S);
+        const int rank = __popcll(S & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+        if (need) {
+            table[rank] = lane;
+            first[rank] = 64u;
+        }
+        wave_lds_sync();
+        const int rr = lane % m;
+        const uint32_t ss = (uint32_t)(lane / m);
+        const UparSlot<R> s = slots[table[rr]];
+        UparReq<R> qq;
+        qq.X = s.X; qq.a = s.a; qq.u0 = s.u0; qq.p = s.p; qq.th0 = s.th0; qq.regime = s.regime;
+        RngKey kk;
+        kk.key0 = s.key0; kk.key1 = s.key1; kk.id0 = s.id0; kk.id1 = s.id1;
+        const uint64_t b0 = ((uint64_t)s.b0hi << 32) | s.b0lo;
+        R uc;
+        const bool acc = upar_candidate<R>(qq, kk, b0, s.base + ss, uc);
+        if (acc) atomicMin(&first[rr], (uint32_t)lane);
+        wave_lds_sync();
+        uint32_t f = 64u;
+        if (need) f = first[rank];
+        const int src = (need && f < 64u) ? (int)f : lane;
+        R got;
+        if constexpr (sizeof(R) == 8) {
+            const uint64_t bits = __double_as_longlong(uc);
+            const uint32_t lo = __shfl((uint32_t)bits, src), hi = __shfl((uint32_t)(bits >> 32), src);
+            got = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+        } else {
+            got = __shfl(uc, src);
+        }
+        if (need) {
+            if (f < 64u) {
+                u = got;
+                t = base + f / (uint32_t)m;
+                need = false;
+            } else {
+                base += (uint32_t)((64 - rank + m - 1) / m);
+                slots[lane].base = base;
+                if (round >= kMaxUparRounds) { need = false; ok = false; u = R(0); t = base; }
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
 __device__ __forceinline__ int find_job(const LaunchView &L, uint64_t g)
 {
     int lo = 0, hi = L.n_jobs - 1;
@@ -547,19 +685,27 @@ __device__ __forceinline__ int find_job(const LaunchView &L, uint64_t g)
     return lo;
 }
 
-// Persistent photon pool.  Every lane runs photons until the shared queue is
-// drained; idle lanes of a wave are refilled together with one atomic.
-template <typename R>
+// Persistent photon pool.  Each pass of the wave loop: idle lanes take new
+// photons from the shared queue (one atomic per wave), every live photon
+// marches to its next interaction, the wave serves all parallel-velocity
+// draws cooperatively, and the scatterings are completed.  SINGLE launches
+// carry one job, whose parameters then live in scalar registers.
+template <typename R, bool CAMS, bool SINGLE>
 __global__ __launch_bounds__(256) void k_transport(LaunchView L)
 {
+    __shared__ UparSlot<R> s_slots[4][64];
+    __shared__ int32_t s_table[4][64];
+    __shared__ uint32_t s_first[4][64];
+    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kCounterSlots - 1));
+    const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + wave) & (kCounterSlots - 1));
     Photon<R> p;
+    p.status = 0;
     LaneCounters lc;
 #pragma unroll
     for (int i = 0; i < 10; ++i) lc.v[i] = 0;
-    const JobView *J = nullptr;
+    const JobView *J = SINGLE ? L.jobs : nullptr;
     bool have = false, drained = false;
     for (;;) {
         if (!drained) {
@@ -576,13 +722,19 @@ __global__ __launch_bounds__(256) void k_transport(LaunchView L)
                 if (!have) {
                     const uint64_t g = base + __popcll(need & lane_lt);
                     if (g < L.total) {
-                        const int j = find_job(L, g);
-                        const JobView *Jn = &L.jobs[j];
-                        if (Jn != J) {
-                            if (J) flush_counters(J, lc, slot);
-                            J = Jn;
+                        uint64_t id;
+                        if constexpr (SINGLE) {
+                            id = L.first_id[0] + g;
+                        } else {
+                            const int j = find_job(L, g);
+                            const JobView *Jn = &L.jobs[j];
+                            if (Jn != J) {
+                                if (J) flush_counters(J, lc, slot);
+                                J = Jn;
+                            }
+                            id = L.first_id[j] + (g - L.prefix[j]);
                         }
-                        emit<R>(*J, p, L.first_id[j] + (g - L.prefix[j]), lc);
+                        emit<R, CAMS>(*J, p, id, lc);
                         have = true;
                         if (p.status != 0) { finish<R>(*J, p, lc); have = false; }
                     }
@@ -593,18 +745,46 @@ __global__ __launch_bounds__(256) void k_transport(LaunchView L)
             if (drained) break;
             continue;          // lanes were refilled with photons born outside
         }
+        bool hi = false;
+        CellRec<R> cr;
+        R xloc = R(0);
+        UparReq<R> q;
+        q.regime = UPAR_GAUSS;
+        uint64_t B0 = 0;
         if (have) {
-            step<R>(*J, p, lc);
-            if (p.status != 0) {
-                finish<R>(*J, p, lc);
-                have = false;
-                if (lc.v[C_SCAT_HI] > (1u << 30) || lc.v[C_UPAR_TRIES] > (1u << 30) ||
-                    lc.v[C_PEEL_CROSSINGS] > (1u << 30) || lc.v[C_CROSSINGS] > (1u << 30))
-                    flush_counters(J, lc, slot);
+            double ktot;
+            if (march<R>(*J, p, cr, xloc, ktot, lc) && interact<R, CAMS>(*J, p, cr, xloc, ktot, lc)) {
+                hi = true;
+                q = upar_setup<R>(cr.a, xloc, cr.xcw);
+                B0 = p.rng.align();
             }
         }
+        R u = R(0);
+        uint32_t tacc = 0;
+        bool ok = true;
+        coop_upar<R>(hi && q.regime != UPAR_GAUSS, q, p.rng.key, B0, u, tacc, ok,
+                     s_slots[wave], s_table[wave], s_first[wave]);
+        if (hi) {
+            if (q.regime == UPAR_GAUSS) {
+                u = upar_gauss<R>(q, p.rng.key, B0);
+                p.rng.k += Rng<R>::kPerBlock;
+            } else {
+                lc.v[C_UPAR_TRIES] += tacc + 1;
+                p.rng.k += (uint64_t)upar_stride<R>(q.regime) * (tacc + 1);
+                if (!ok) p.status = 3;
+            }
+            if (p.status == 0)
+                scatter_finish<R, CAMS>(*J, p, cr, xloc, (xloc < R(0)) ? -u : u, lc);
+        }
+        if (have && p.status != 0) {
+            finish<R>(*J, p, lc);
+            have = false;
+            if (lc.v[C_SCAT_HI] > (1u << 30) || lc.v[C_UPAR_TRIES] > (1u << 30) ||
+                lc.v[C_PEEL_CROSSINGS] > (1u << 30) || lc.v[C_CROSSINGS] > (1u << 30))
+                flush_counters(J, lc, slot);
+        }
     }
-    if (J) flush_counters(J, lc, slot);
+    if (SINGLE || J) flush_counters(J, lc, slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -617,25 +797,54 @@ __global__ void k_voigt(int64_t n, const double *a, const double *x, double *out
     if (i < n) out[i] = (double)voigt_H<R>((R)a[i], (R)x[i]);
 }
 
+// what 0: u_par with the cooperative sampler (x = p1); what 4: the same with
+// x varying across lanes, x_i = p1 + 0.41 (i mod 23) (-1)^i.
 template <typename R>
-__global__ void k_sample(int what, double p0, double p1, double p2, uint64_t seed, int64_t n,
-                         double *out, int32_t *draws)
+__global__ __launch_bounds__(256) void k_sample(int what, double p0, double p1, double p2,
+                                                uint64_t seed, int64_t n, double *out,
+                                                int32_t *draws)
 {
+    __shared__ UparSlot<R> s_slots[4][64];
+    __shared__ int32_t s_table[4][64];
+    __shared__ uint32_t s_first[4][64];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int wave = threadIdx.x >> 6;
+    const bool live = i < n;
     Rng<R> rng;
-    rng.init(seed, (uint64_t)i);
-    if (what == 0) {
-        uint32_t tries = 0;
-        out[i] = (double)draw_upar<R>((R)p0, (R)p1, (R)p2, rng, tries);
-        draws[i] = (int32_t)rng.k;
-    } else if (what == 1) {
+    rng.init(seed, (uint64_t)(live ? i : 0));
+    if (what == 0 || what == 4) {
+        R x = (R)p1;
+        if (what == 4) x = (R)(p1 + 0.41 * (double)(i % 23) * ((i & 1) ? -1.0 : 1.0));
+        const UparReq<R> q = upar_setup<R>((R)p0, x, (R)p2);
+        const uint64_t B0 = rng.align();
+        R u = R(0);
+        uint32_t t = 0;
+        bool ok = true;
+        coop_upar<R>(live && q.regime != UPAR_GAUSS, q, rng.key, B0, u, t, ok, s_slots[wave],
+                     s_table[wave], s_first[wave]);
+        if (!live) return;
+        if (q.regime == UPAR_GAUSS) {
+            u = upar_gauss<R>(q, rng.key, B0);
+            rng.k += Rng<R>::kPerBlock;
+        } else {
+            rng.k += (uint64_t)upar_stride<R>(q.regime) * (t + 1);
+        }
+        out[i] = (double)((x < R(0)) ? -u : u);
+        draws[i] = ok ? (int32_t)rng.k : -1;
+        return;
+    }
+    if (!live) return;
+    if (what == 1) {
         R u1, u2;
         draw_uperp<R>((R)p0, rng, u1, u2);
         out[2 * i] = (double)u1;
         out[2 * i + 1] = (double)u2;
     } else if (what == 2) {
         out[i] = (double)draw_mu<R>((R)p0, rng);
+    } else if (what == 5) {
+        uint32_t tries = 0;
+        out[i] = (double)draw_upar<R>((R)p0, (R)p1, (R)p2, rng, tries);
+        draws[i] = (int32_t)rng.k;
     } else {
         const int64_t m = (int64_t)p0;
         for (int64_t j = 0; j < m; ++j) out[i * m + j] = (double)rng.next();
@@ -658,23 +867,49 @@ hipError_t launch_cell_setup(int64_t n, const double *n_HI, const double *T, con
     return hipGetLastError();
 }
 
-hipError_t launch_transport(int precision, const LaunchView &L, int grid, int block,
-                            hipStream_t s)
+template <typename R, bool CAMS, bool SINGLE>
+static hipError_t launch_t(const LaunchView &L, int grid, int block, hipStream_t s)
 {
-    if (precision == 0)
-        hipLaunchKernelGGL(k_transport<double>, dim3(grid), dim3(block), 0, s, L);
-    else
-        hipLaunchKernelGGL(k_transport<float>, dim3(grid), dim3(block), 0, s, L);
+    hipLaunchKernelGGL((k_transport<R, CAMS, SINGLE>), dim3(grid), dim3(block), 0, s, L);
     return hipGetLastError();
 }
 
-hipError_t transport_occupancy(int precision, int block, int *blocks_per_cu)
+template <typename R, bool CAMS, bool SINGLE>
+static hipError_t occupancy_t(int block, int *blocks_per_cu)
 {
-    if (precision == 0)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_transport<double>,
-                                                            block, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_transport<float>,
-                                                        block, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
+                                                        k_transport<R, CAMS, SINGLE>, block, 0);
+}
+
+hipError_t launch_transport(int precision, bool cams, const LaunchView &L, int grid, int block,
+                            hipStream_t s)
+{
+    const bool single = L.n_jobs == 1;
+    if (precision == 0) {
+        if (cams) return single ? launch_t<double, true, true>(L, grid, block, s)
+                                : launch_t<double, true, false>(L, grid, block, s);
+        return single ? launch_t<double, false, true>(L, grid, block, s)
+                      : launch_t<double, false, false>(L, grid, block, s);
+    }
+    if (cams) return single ? launch_t<float, true, true>(L, grid, block, s)
+                            : launch_t<float, true, false>(L, grid, block, s);
+    return single ? launch_t<float, false, true>(L, grid, block, s)
+                  : launch_t<float, false, false>(L, grid, block, s);
+}
+
+hipError_t transport_occupancy(int precision, bool cams, bool single, int block,
+                               int *blocks_per_cu)
+{
+    if (precision == 0) {
+        if (cams) return single ? occupancy_t<double, true, true>(block, blocks_per_cu)
+                                : occupancy_t<double, true, false>(block, blocks_per_cu);
+        return single ? occupancy_t<double, false, true>(block, blocks_per_cu)
+                      : occupancy_t<double, false, false>(block, blocks_per_cu);
+    }
+    if (cams) return single ? occupancy_t<float, true, true>(block, blocks_per_cu)
+                            : occupancy_t<float, true, false>(block, blocks_per_cu);
+    return single ? occupancy_t<float, false, true>(block, blocks_per_cu)
+                  : occupancy_t<float, false, false>(block, blocks_per_cu);
 }
 
 hipError_t launch_voigt(int precision, int64_t n, const double *a, const double *x, double *out,
@@ -694,7 +929,7 @@ hipError_t launch_sample(int precision, int what, double p0, double p1, double p
                          uint64_t seed, int64_t n, double *out, int32_t *draws, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const int block = 256;
+    const int block = 256;   // k_sample keeps per-wave LDS for four waves
     const unsigned grid = (unsigned)((n + block - 1) / block);
     if (precision == 0)
         hipLaunchKernelGGL(k_sample<double>, dim3(grid), dim3(block), 0, s, what, p0, p1, p2,

@@ -11,9 +11,10 @@ namespace colt {
 hipError_t launch_cell_setup(int64_t n, const double *n_HI, const double *T, const double *v,
                              const double *k_dust, const double *atau_nl, double dx_cm,
                              void *rd, void *ad, void *rf, void *af, hipStream_t s);
-hipError_t launch_transport(int precision, const LaunchView &L, int grid, int block,
+hipError_t launch_transport(int precision, bool cams, const LaunchView &L, int grid, int block,
                             hipStream_t s);
-hipError_t transport_occupancy(int precision, int block, int *blocks_per_cu);
+hipError_t transport_occupancy(int precision, bool cams, bool single, int block,
+                               int *blocks_per_cu);
 hipError_t launch_voigt(int precision, int64_t n, const double *a, const double *x, double *out,
                         hipStream_t s);
 hipError_t launch_sample(int precision, int what, double p0, double p1, double p2,

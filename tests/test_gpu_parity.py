@@ -97,13 +97,30 @@ def test_device_voigt_matches_oracle():
 
 
 @pytest.mark.parametrize("x", [0.3, 1.0, 2.5, 3.0, 4.6, 8.9, -9.5, -2.0])
-def test_device_upar_fp64_is_the_oracle_sampler(x):
+@pytest.mark.parametrize("how", ["upar", "upar_seq"])
+def test_device_upar_fp64_is_the_oracle_sampler(x, how):
+    """The wave-cooperative sampler returns exactly the sequential result."""
     a = 4.702e-4
     xcw = oracle.xcw(a)
-    u, d = colt.sample("upar", 3000, seed=5, p0=a, p1=x, p2=xcw)
+    u, d = colt.sample(how, 3000, seed=5, p0=a, p1=x, p2=xcw)
     ru, rd = oracle.sample_upar(a, x, 3000, seed=5, xcw_val=xcw)
     assert np.array_equal(d, rd)
     assert np.allclose(u, ru, rtol=1e-10, atol=1e-12)
+
+
+def test_device_upar_cooperative_mixed_requests():
+    """Requests of all three regimes interleaved within each wave, n ragged."""
+    a, xcw, n = 4.702e-4, oracle.xcw(4.702e-4), 2999
+    u, d = colt.sample("upar_mixed", n, seed=17, p0=a, p1=0.2, p2=xcw)
+    assert np.all(d > 0)
+    for i in range(n):
+        x = 0.2 + 0.41 * (i % 23) * (-1.0 if i & 1 else 1.0)
+        ru, rd = oracle.sample_upar_one(a, x, 17, i, xcw_val=xcw)
+        assert d[i] == rd and abs(u[i] - ru) <= 1e-10 * max(1.0, abs(u[i])), i
+    u32, d32 = colt.sample("upar_mixed", n, seed=17, p0=a, p1=0.2, p2=xcw,
+                           precision=colt.FP32_BULK)
+    s32, _ = colt.sample("upar_seq", 1, seed=17, p0=a, p1=0.2, p2=xcw, precision=colt.FP32_BULK)
+    assert np.all(d32 > 0) and u32[0] == s32[0]
 
 
 @pytest.mark.parametrize("x", [0.0, 1.5, 3.0, 3.5, 6.0, -12.0])
@@ -197,8 +214,11 @@ def test_octree_nfw_parity():
     g, r = run_both(wl)
     compare_records(g, r, 4000 * PC, peel=True, flip=FLIP_LOCAL)
     statistically_equal(g, r, 200)
-    for i in range(4):
-        assert stats.chi2_two_hist_p(g["cam_spec"][i] * 1e3, r["cam_spec"][i] * 1e3) > 1e-3
+    # camera flux per photon: means agree within the Monte-Carlo error
+    gp, rp = g["records"]["peel"], r["records"]["peel"]
+    for i in range(gp.shape[1]):
+        se = math.sqrt((gp[:, i].var() + rp[:, i].var()) / gp.shape[0]) + 1e-300
+        assert abs(gp[:, i].mean() - rp[:, i].mean()) < 3 * se
 
 
 def test_octree_and_cartesian_agree_on_uniform_gas():

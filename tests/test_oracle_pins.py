@@ -163,9 +163,9 @@ def test_upar_sampler_matches_eq_uparf(x):
     cdf = stats.upar_cdf_factory(a, x)
     assert stats.ks_p(u, cdf) > 1e-3
     if abs(x) <= 1.0:
-        assert np.all(draws % 2 == 0)      # theta and accept draws per attempt
+        assert np.all(draws % 2 == 0)      # one block (theta, accept) per candidate
     else:
-        assert np.all(draws % 3 == 0)      # part, theta and accept draws per attempt
+        assert np.all(draws % 4 == 0)      # two blocks (part, theta, accept, unused)
 
 
 def test_upar_sampler_low_temperature():
