@@ -65,6 +65,8 @@ typedef int32_t colt_status;
 #define COLT_C_UPAR_TRIES     7   /* candidate draws of the u_par rejection sampler   */
 #define COLT_C_PEEL_CROSSINGS 8   /* cell crossings of next-event marches             */
 #define COLT_C_CAPPED         9   /* photons stopped by the per-photon event cap      */
+#define COLT_C_UPAR_ROUNDS   10   /* cooperative u_par rounds, summed over waves      */
+#define COLT_C_PASSES        11   /* transport-loop passes, summed over waves         */
 
 typedef struct colt_grid_s *colt_grid;
 typedef struct colt_job_s *colt_job;
@@ -174,6 +176,16 @@ typedef struct {
  * octree), COLT_ERR_NOMEM, COLT_ERR_HIP. */
 colt_status colt_init_grid(const colt_grid_desc *desc, const colt_allocator *alloc,
                            void *stream, colt_grid *out);
+
+/* Computes the non-local a*tau estimate of every cell on the device (Sec.
+ * 3.2.4, eq. atauNL): six coordinate-axis paths start at the centres of the
+ * cell's faces and run outward, summing a * tau0 = a n_HI sigma0 l over the
+ * cells crossed while |n_HI - n_HI,start| < f_nl n_HI,start (stopping at the
+ * domain edge); the estimate is the smallest sum.  It replaces the grid's
+ * aτ_NL array, which local core-skipping adds to a tau_cell.  f_nl = 0 gives
+ * zeros.  Synchronous on `stream`.  Errors: COLT_ERR_ARG (f_nl < 0),
+ * COLT_ERR_STATE (jobs registered on the grid), COLT_ERR_HIP. */
+colt_status colt_grid_nonlocal(colt_grid grid, double f_nl, void *stream);
 
 /* Registers a transfer job on a grid: sources, photon count, physics options
  * and tally layout.  Allocates and zeroes the job's device tallies on the

@@ -72,6 +72,8 @@ def lib():
         L.orc_run.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Source),
                               ctypes.POINTER(_Params), ctypes.POINTER(_Out), ctypes.c_int]
         L.orc_run.restype = ctypes.c_int
+        L.orc_nonlocal.argtypes = [ctypes.POINTER(_Grid), ctypes.c_double, _dp]
+        L.orc_nonlocal.restype = None
         L.orc_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
         L.orc_philox4x32_10.restype = None
         L.orc_uniform.argtypes = [ctypes.c_uint64] * 3
@@ -182,6 +184,41 @@ def _f64(a, shape=None):
     return a if shape is None else a.reshape(shape)
 
 
+def _grid_struct(grid, hold):
+    g = _Grid()
+    g.kind = int(grid["kind"])
+    g.nx, g.ny, g.nz = (int(v) for v in grid.get("shape", (0, 0, 0)))
+    g.box_min[:] = [float(v) for v in grid["box_min"]]
+    g.box_max[:] = [float(v) for v in grid["box_max"]]
+    n_cells = int(np.asarray(grid["n_HI"]).size)
+    g.n_nodes = n_cells
+    child = grid.get("child")
+    if child is not None:
+        child = hold("child", np.ascontiguousarray(child, dtype=np.int32))
+    g.child = _ptr(child, _ip)
+    g.n_HI = _ptr(hold("n", _f64(grid["n_HI"])))
+    g.T = _ptr(hold("T", _f64(grid["T"])))
+    g.v = _ptr(hold("v", _f64(grid.get("v"))))
+    g.k_dust = _ptr(hold("kd", _f64(grid.get("k_dust"))))
+    g.atau_nl = _ptr(hold("nl", _f64(grid.get("atau_nl"))))
+    g.dust_albedo = float(grid.get("albedo", 0.0))
+    g.escape_radius = float(grid.get("escape_radius", 0.0))
+    return g
+
+
+def nonlocal_atau(grid, f_nl):
+    """Non-local a*tau estimate per cell / octree node (Sec. 3.2.4)."""
+    keep = {}
+
+    def hold(name, arr):
+        keep[name] = arr
+        return arr
+    g = _grid_struct(grid, hold)
+    out = np.zeros(int(np.asarray(grid["n_HI"]).size))
+    lib().orc_nonlocal(ctypes.byref(g), float(f_nl), _ptr(out))
+    return out
+
+
 def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=None):
     """Runs photons [id_begin, id_end) of a job through the oracle.
 
@@ -202,24 +239,7 @@ def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=No
         keep[name] = arr
         return arr
 
-    g = _Grid()
-    g.kind = int(grid["kind"])
-    g.nx, g.ny, g.nz = (int(v) for v in grid.get("shape", (0, 0, 0)))
-    g.box_min[:] = [float(v) for v in grid["box_min"]]
-    g.box_max[:] = [float(v) for v in grid["box_max"]]
-    n_cells = int(np.asarray(grid["n_HI"]).size)
-    g.n_nodes = n_cells
-    child = grid.get("child")
-    if child is not None:
-        child = hold("child", np.ascontiguousarray(child, dtype=np.int32))
-    g.child = _ptr(child, _ip)
-    g.n_HI = _ptr(hold("n", _f64(grid["n_HI"])))
-    g.T = _ptr(hold("T", _f64(grid["T"])))
-    g.v = _ptr(hold("v", _f64(grid.get("v"))))
-    g.k_dust = _ptr(hold("kd", _f64(grid.get("k_dust"))))
-    g.atau_nl = _ptr(hold("nl", _f64(grid.get("atau_nl"))))
-    g.dust_albedo = float(grid.get("albedo", 0.0))
-    g.escape_radius = float(grid.get("escape_radius", 0.0))
+    g = _grid_struct(grid, hold)
 
     s = _Source()
     pos = hold("pos", _f64(source["pos"]).reshape(-1))

@@ -98,6 +98,10 @@ typedef struct {
 int orc_run(const orc_grid *g, const orc_source *s, const orc_params *p, orc_out *o,
             int n_threads);
 
+/* Non-local a*tau per cell (Sec. 3.2.4, eq. atauNL) with density threshold
+ * f_NL; out has one entry per cell (Cartesian) or node (octree). */
+void orc_nonlocal(const orc_grid *g, double f_nl, double *out);
+
 /* Building blocks exported for the pin tests. */
 void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_uniform(uint64_t seed, uint64_t photon, uint64_t k);

@@ -161,3 +161,90 @@ double orc_min_face_distance(const orc_cell *c, const double r[3])
     }
     return (m < 0.0) ? 0.0 : m;
 }
+
+/* Non-local a*tau estimate of Sec. 3.2.4 (eq. atauNL): for every cell, six
+ * paths along the coordinate axes start at the centre of one of the cell's
+ * faces and run outward, summing a * tau0 = a n_HI sigma0 l over the cells
+ * crossed while |n_HI - n_HI,start| < f_NL n_HI,start; the estimate is the
+ * smallest of the six sums.  f_NL = 0 gives zero everywhere.  Octree output
+ * is per node (internal nodes get 0). */
+static double nonlocal_cell(const orc_grid *g, const orc_cell *c0, double f_nl)
+{
+    double n_start = g->n_HI[c0->id];
+    double best = INFINITY;
+    for (int d = 0; d < 3; ++d) {
+        for (int s = -1; s <= 1; s += 2) {
+            double p[3], k[3] = { 0.0, 0.0, 0.0 };
+            k[d] = (double)s;
+            for (int e = 0; e < 3; ++e) p[e] = 0.5 * (c0->lo[e] + c0->hi[e]);
+            p[d] = (s > 0) ? c0->hi[d] : c0->lo[d];
+            double sum = 0.0;
+            orc_cell c;
+            if (orc_locate(g, p, k, &c)) {
+                for (;;) {
+                    double n = g->n_HI[c.id];
+                    if (!(fabs(n - n_start) < f_nl * n_start)) break;
+                    double a, sigma0, k0, vth, xcw, gr;
+                    orc_cell_constants(g->T[c.id], n, &a, &sigma0, &k0, &vth, &xcw, &gr);
+                    int axis, by_sphere;
+                    double l = orc_exit_distance(g, &c, p, k, &axis, &by_sphere);
+                    sum += a * k0 * l;
+                    if (by_sphere) break;
+                    p[d] += l * k[d];
+                    if (!orc_cross(g, &c, p, k, axis)) break;
+                }
+            }
+            if (sum < best) best = sum;
+        }
+    }
+    return best;
+}
+
+static void nonlocal_octree(const orc_grid *g, int64_t node, int64_t I[3], int64_t S,
+                            double unit, double f_nl, double *out)
+{
+    if (g->child[node] >= 0) {
+        int64_t half = S / 2;
+        for (int o = 0; o < 8; ++o) {
+            int64_t J[3] = { I[0] + ((o & 1) ? half : 0), I[1] + ((o & 2) ? half : 0),
+                             I[2] + ((o & 4) ? half : 0) };
+            nonlocal_octree(g, g->child[node] + o, J, half, unit, f_nl, out);
+        }
+        return;
+    }
+    orc_cell c;
+    c.id = node;
+    c.S = S;
+    for (int d = 0; d < 3; ++d) {
+        c.I[d] = I[d];
+        c.ijk[d] = 0;
+        c.lo[d] = g->box_min[d] + (double)I[d] * unit;
+        c.hi[d] = g->box_min[d] + (double)(I[d] + S) * unit;
+    }
+    out[node] = nonlocal_cell(g, &c, f_nl);
+}
+
+void orc_nonlocal(const orc_grid *g, double f_nl, double *out)
+{
+    if (g->kind == 0) {
+        int n[3] = { g->nx, g->ny, g->nz };
+        for (int iz = 0; iz < n[2]; ++iz)
+            for (int iy = 0; iy < n[1]; ++iy)
+                for (int ix = 0; ix < n[0]; ++ix) {
+                    orc_cell c;
+                    c.ijk[0] = ix; c.ijk[1] = iy; c.ijk[2] = iz;
+                    for (int d = 0; d < 3; ++d) {
+                        double w = (g->box_max[d] - g->box_min[d]) / n[d];
+                        c.lo[d] = g->box_min[d] + c.ijk[d] * w;
+                        c.hi[d] = g->box_min[d] + (c.ijk[d] + 1) * w;
+                    }
+                    c.id = ((int64_t)iz * n[1] + iy) * n[0] + ix;
+                    out[c.id] = nonlocal_cell(g, &c, f_nl);
+                }
+        return;
+    }
+    for (int64_t i = 0; i < g->n_nodes; ++i) out[i] = 0.0;
+    const double unit = (g->box_max[0] - g->box_min[0]) / (double)((int64_t)1 << ORC_OCT_DEPTH);
+    int64_t I[3] = { 0, 0, 0 };
+    nonlocal_octree(g, 0, I, (int64_t)1 << ORC_OCT_DEPTH, unit, f_nl, out);
+}

@@ -19,12 +19,12 @@ FP64 = 0
 FP32_BULK = 1
 N_COUNTERS = 16
 COUNTER_NAMES = ["emitted", "escaped", "absorbed", "scat_hi", "scat_dust", "crossings",
-                 "peels", "upar_tries", "peel_crossings", "capped"]
+                 "peels", "upar_tries", "peel_crossings", "capped", "upar_rounds", "passes"]
 
 EXPORTS = ["colt_init_grid", "colt_emit", "colt_transport", "colt_tally", "colt_job_status",
            "colt_grid_bytes", "colt_job_bytes", "colt_last_kernel_ms", "colt_release_job",
            "colt_release_grid", "colt_last_error", "colt_grid_fields", "colt_eval_voigt",
-           "colt_sample"]
+           "colt_sample", "colt_grid_nonlocal"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -112,13 +112,14 @@ def lib():
         L.colt_release_grid.argtypes = [vp]
         L.colt_last_error.restype = ctypes.c_char_p
         L.colt_grid_fields.argtypes = [vp, _dp]
+        L.colt_grid_nonlocal.argtypes = [vp, ctypes.c_double, vp]
         L.colt_eval_voigt.argtypes = [ctypes.c_int32, _dp, _dp, ctypes.c_int64, _dp, vp]
         L.colt_sample.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                                   ctypes.c_int64, _dp, _ip, vp]
         for name in ("colt_init_grid", "colt_emit", "colt_transport", "colt_tally",
                      "colt_job_status", "colt_release_grid", "colt_grid_fields",
-                     "colt_eval_voigt", "colt_sample"):
+                     "colt_eval_voigt", "colt_sample", "colt_grid_nonlocal"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -221,6 +222,13 @@ class Grid:
         self.handle = h
         self.kind = d.kind
         self.n_leaves = int(np.sum(np.asarray(child) < 0)) if d.kind == 1 else n_cells
+        f_nl = float(grid.get("f_nl", 0.0))
+        if f_nl > 0.0:
+            self.nonlocal_estimate(f_nl)
+
+    def nonlocal_estimate(self, f_nl):
+        """Replaces the per-cell non-local a*tau with the device estimate."""
+        _check(lib().colt_grid_nonlocal(self.handle, float(f_nl), self.stream))
 
     @property
     def nbytes(self):

@@ -132,6 +132,8 @@ struct colt_grid_s {
     DevMem mem;
     GridView view{};               // cells/aux point at the FP64 records
     void *rec_d = nullptr, *aux_d = nullptr, *rec_f = nullptr, *aux_f = nullptr;
+    double *n_dev = nullptr;       // n_HI per cell / leaf (for the non-local estimate)
+    std::vector<int32_t> child_host, base_host;   // octree tables as uploaded
     int32_t kind = 0;
     int64_t n_leaves = 0;
     double dx_cm = 0.0;
@@ -286,12 +288,13 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
     void *ad = g->mem.get((size_t)nl * sizeof(CellAux<double>));
     void *rf = g->mem.get((size_t)nl * sizeof(CellRec<float>));
     void *af = g->mem.get((size_t)nl * sizeof(CellAux<float>));
+    g->n_dev = (double *)g->mem.get((size_t)nl * sizeof(double));
     void *dchild = nullptr, *dbase = nullptr;
     if (d->kind == 1) {
         dchild = g->mem.get(child_dev.size() * sizeof(int32_t));
         dbase = g->mem.get(base_dev.size() * sizeof(int32_t));
     }
-    if (!stage || !rd || !ad || !rf || !af || (d->kind == 1 && (!dchild || !dbase))) {
+    if (!stage || !rd || !ad || !rf || !af || !g->n_dev || (d->kind == 1 && (!dchild || !dbase))) {
         g->mem.release_all();
         delete g;
         return fail(COLT_ERR_NOMEM, "device allocation for the grid failed");
@@ -310,6 +313,8 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
     if (e == hipSuccess)
         e = launch_cell_setup(nl, sd, sd + nl, sd + 4 * nl, sd + 2 * nl, sd + 3 * nl, g->dx_cm,
                               rd, ad, rf, af, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->n_dev, sd, (size_t)nl * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         cleanup();
@@ -331,7 +336,62 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
     v.esc_r = d->escape_radius / g->dx_cm;
     v.albedo = d->dust_albedo;
     g->rec_d = rd; g->aux_d = ad; g->rec_f = rf; g->aux_f = af;
+    if (d->kind == 1) {
+        g->child_host = std::move(child_dev);
+        g->base_host = std::move(base_dev);
+    }
     *out = g;
+    return COLT_OK;
+}
+
+colt_status colt_grid_nonlocal(colt_grid g, double f_nl, void *stream)
+{
+    if (!g) return fail(COLT_ERR_ARG, "null grid");
+    if (!(f_nl >= 0.0) || !std::isfinite(f_nl)) return fail(COLT_ERR_ARG, "f_nl must be >= 0");
+    if (g->jobs.load() > 0) return fail(COLT_ERR_STATE, "grid has live jobs");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nl = g->n_leaves;
+    double *boxes = nullptr;
+    if (g->kind == 1) {
+        // lower corner and size of every leaf, in base-cell units
+        std::vector<double> hb((size_t)nl * 4);
+        const int nb = g->view.n[0];
+        struct Item { int32_t node; double lo[3]; double size; };
+        std::vector<Item> stack;
+        for (int iz = 0; iz < nb; ++iz)
+            for (int iy = 0; iy < nb; ++iy)
+                for (int ix = 0; ix < nb; ++ix) {
+                    stack.push_back({g->base_host[((size_t)iz * nb + iy) * nb + ix],
+                                     {(double)ix, (double)iy, (double)iz}, 1.0});
+                    while (!stack.empty()) {
+                        Item it = stack.back();
+                        stack.pop_back();
+                        const int32_t c = g->child_host[it.node];
+                        if (c < 0) {
+                            double *o = &hb[(size_t)(-c - 1) * 4];
+                            o[0] = it.lo[0]; o[1] = it.lo[1]; o[2] = it.lo[2]; o[3] = it.size;
+                            continue;
+                        }
+                        const double h = 0.5 * it.size;
+                        for (int oc = 0; oc < 8; ++oc)
+                            stack.push_back({c + oc,
+                                             {it.lo[0] + ((oc & 1) ? h : 0.0),
+                                              it.lo[1] + ((oc & 2) ? h : 0.0),
+                                              it.lo[2] + ((oc & 4) ? h : 0.0)}, h});
+                    }
+                }
+        HIP_TRY(hipMalloc(&boxes, hb.size() * sizeof(double)));
+        hipError_t e = hipMemcpy(boxes, hb.data(), hb.size() * sizeof(double),
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(boxes);
+            return fail(COLT_ERR_HIP, "leaf boxes upload: %s", hipGetErrorString(e));
+        }
+    }
+    hipError_t e = launch_nonlocal(g->view, g->n_dev, boxes, nl, f_nl, g->aux_d, g->aux_f, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (boxes) (void)hipFree(boxes);
+    if (e != hipSuccess) return fail(COLT_ERR_HIP, "non-local estimate: %s", hipGetErrorString(e));
     return COLT_OK;
 }
 

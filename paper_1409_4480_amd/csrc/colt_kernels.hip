@@ -14,6 +14,10 @@
 #include "colt_internal.h"
 #include "colt_launch.h"
 
+#ifndef COLT_FP32_MIN_BLOCKS
+#define COLT_FP32_MIN_BLOCKS 3
+#endif
+
 namespace colt {
 
 // ---------------------------------------------------------------------------
@@ -236,18 +240,21 @@ __device__ __forceinline__ int bin_of(double x, double lo, double hi, int n)
 }
 
 // Per-lane event counters, flushed to the job's spread counter slots.
+constexpr int kLaneCounters = 12;
 struct LaneCounters {
-    uint32_t v[10];
+    uint32_t v[kLaneCounters];
 };
 
+// C_ROUNDS (cooperative sampler rounds) and C_PASSES (wave-loop passes) are
+// counted once per wave, by its first lane.
 enum { C_EMITTED = 0, C_ESCAPED, C_ABSORBED, C_SCAT_HI, C_SCAT_DUST, C_CROSSINGS, C_PEELS,
-       C_UPAR_TRIES, C_PEEL_CROSSINGS, C_CAPPED };
+       C_UPAR_TRIES, C_PEEL_CROSSINGS, C_CAPPED, C_ROUNDS, C_PASSES };
 
 __device__ __forceinline__ void flush_counters(const JobView *J, LaneCounters &lc, int slot)
 {
     unsigned long long *dst = J->counters + (size_t)slot * kNumCounters;
 #pragma unroll
-    for (int i = 0; i < 10; ++i) {
+    for (int i = 0; i < kLaneCounters; ++i) {
         if (lc.v[i]) atomicAdd(dst + i, (unsigned long long)lc.v[i]);
         lc.v[i] = 0;
     }
@@ -611,13 +618,15 @@ constexpr uint32_t kMaxUparRounds = 1u << 22;   // bound on rounds; never reache
 // `need` hold the unsigned |u_par| in u and the accepted candidate number in t
 // (ok = false only if the round bound was hit).
 template <typename R>
-__device__ __forceinline__ void coop_upar(bool need, const UparReq<R> &q, const RngKey &key,
-                                          uint64_t B0, R &u, uint32_t &t, bool &ok,
-                                          UparSlot<R> *slots, int32_t *table, uint32_t *first)
+__device__ __forceinline__ uint32_t coop_upar(bool need, const UparReq<R> &q, const RngKey &key,
+                                              uint64_t B0, R &u, uint32_t &t, bool &ok,
+                                              UparSlot<R> *slots, int32_t *table,
+                                              uint32_t *first)
 {
     const int lane = threadIdx.x & 63;
     ok = true;
     uint32_t base = 0;
+    uint32_t rounds = 0;
     if (need) {
         UparSlot<R> s;
         s.X = q.X; s.a = q.a; s.u0 = q.u0; s.p = q.p; s.th0 = q.th0; s.regime = q.regime;
@@ -629,6 +638,7 @@ __device__ __forceinline__ void coop_upar(bool need, const UparReq<R> &q, const 
     for (uint32_t round = 0;; ++round) {
         const uint64_t S = __ballot(need);
         if (S == 0) break;
+        ++rounds;
         const int m = __popcll(S);
         const int rank = __popcll(S & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
         if (need) {
@@ -672,6 +682,7 @@ __device__ __forceinline__ void coop_upar(bool need, const UparReq<R> &q, const 
         }
         wave_lds_sync();
     }
+    return rounds;
 }
 
 __device__ __forceinline__ int find_job(const LaunchView &L, uint64_t g)
@@ -690,8 +701,15 @@ __device__ __forceinline__ int find_job(const LaunchView &L, uint64_t g)
 // marches to its next interaction, the wave serves all parallel-velocity
 // draws cooperatively, and the scatterings are completed.  SINGLE launches
 // carry one job, whose parameters then live in scalar registers.
+// Resident workgroups of 256 lanes per CU the register allocation aims for.
+template <typename R, bool CAMS>
+constexpr int transport_min_blocks()
+{
+    return (sizeof(R) == 4 && !CAMS) ? COLT_FP32_MIN_BLOCKS : 1;
+}
+
 template <typename R, bool CAMS, bool SINGLE>
-__global__ __launch_bounds__(256) void k_transport(LaunchView L)
+__global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_transport(LaunchView L)
 {
     __shared__ UparSlot<R> s_slots[4][64];
     __shared__ int32_t s_table[4][64];
@@ -704,7 +722,7 @@ __global__ __launch_bounds__(256) void k_transport(LaunchView L)
     p.status = 0;
     LaneCounters lc;
 #pragma unroll
-    for (int i = 0; i < 10; ++i) lc.v[i] = 0;
+    for (int i = 0; i < kLaneCounters; ++i) lc.v[i] = 0;
     const JobView *J = SINGLE ? L.jobs : nullptr;
     bool have = false, drained = false;
     for (;;) {
@@ -762,8 +780,13 @@ __global__ __launch_bounds__(256) void k_transport(LaunchView L)
         R u = R(0);
         uint32_t tacc = 0;
         bool ok = true;
-        coop_upar<R>(hi && q.regime != UPAR_GAUSS, q, p.rng.key, B0, u, tacc, ok,
-                     s_slots[wave], s_table[wave], s_first[wave]);
+        const uint32_t rounds = coop_upar<R>(hi && q.regime != UPAR_GAUSS, q, p.rng.key, B0, u,
+                                             tacc, ok, s_slots[wave], s_table[wave],
+                                             s_first[wave]);
+        if (lane == 0 && J) {
+            lc.v[C_ROUNDS] += rounds;
+            ++lc.v[C_PASSES];
+        }
         if (hi) {
             if (q.regime == UPAR_GAUSS) {
                 u = upar_gauss<R>(q, p.rng.key, B0);
@@ -785,6 +808,67 @@ __global__ __launch_bounds__(256) void k_transport(LaunchView L)
         }
     }
     if (SINGLE || J) flush_counters(J, lc, slot);
+}
+
+// ---------------------------------------------------------------------------
+// Non-local a*tau (Sec. 3.2.4, eq. atauNL): per cell, six axis paths from the
+// centres of its faces outward, summing a k0 l over the cells crossed while
+// the density stays within f_NL of the starting cell's; the minimum of the six
+// sums.  One thread per cell; paths end at the domain edge.
+// ---------------------------------------------------------------------------
+__global__ void k_nonlocal(GridView g, const double *__restrict__ n_HI,
+                           const double *__restrict__ leaf_boxes, int64_t n, double f_nl,
+                           CellAux<double> *__restrict__ ad, CellAux<float> *__restrict__ af)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double lo[3], size;
+    if (g.kind == 0) {
+        lo[0] = (double)(i % g.n[0]);
+        lo[1] = (double)((i / g.n[0]) % g.n[1]);
+        lo[2] = (double)(i / ((int64_t)g.n[0] * g.n[1]));
+        size = 1.0;
+    } else {
+        lo[0] = leaf_boxes[4 * i];
+        lo[1] = leaf_boxes[4 * i + 1];
+        lo[2] = leaf_boxes[4 * i + 2];
+        size = leaf_boxes[4 * i + 3];
+    }
+    const double n_start = n_HI[i];
+    double best = __builtin_inf();
+#pragma unroll 1
+    for (int dir = 0; dir < 6; ++dir) {
+        const int d = dir >> 1;
+        const double sgn = (dir & 1) ? -1.0 : 1.0;
+        double p[3], k[3], ik[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            p[e] = lo[e] + 0.5 * size;
+            k[e] = (e == d) ? sgn : 0.0;
+            ik[e] = k[e];
+            if (e == d) p[e] = (sgn > 0.0) ? lo[e] + size : lo[e];
+        }
+        double sum = 0.0;
+        CellBox c;
+        if (locate(g, p, k, c)) {
+            for (;;) {
+                const double nn = n_HI[c.cell];
+                if (!(::fabs(nn - n_start) < f_nl * n_start)) break;
+                const CellRec<double> cr = load_cell<double>(g, c.cell);
+                int axis;
+                bool by_sphere;
+                const double l = exit_distance(g, c, p, k, ik, axis, by_sphere);
+                sum += cr.a * cr.k0 * l;
+                if (by_sphere) break;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) p[e] += l * k[e];
+                if (!cross(g, c, p, k, axis)) break;
+            }
+        }
+        best = (sum < best) ? sum : best;
+    }
+    ad[i].atau_nl = best;
+    af[i].atau_nl = (float)best;
 }
 
 // ---------------------------------------------------------------------------
@@ -910,6 +994,18 @@ hipError_t transport_occupancy(int precision, bool cams, bool single, int block,
                             : occupancy_t<float, true, false>(block, blocks_per_cu);
     return single ? occupancy_t<float, false, true>(block, blocks_per_cu)
                   : occupancy_t<float, false, false>(block, blocks_per_cu);
+}
+
+hipError_t launch_nonlocal(const GridView &g, const double *n_HI, const double *leaf_boxes,
+                           int64_t n, double f_nl, void *ad, void *af, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int block = 128;
+    const unsigned grid = (unsigned)((n + block - 1) / block);
+    GridView gd = g;          // FP64 records
+    hipLaunchKernelGGL(k_nonlocal, dim3(grid), dim3(block), 0, s, gd, n_HI, leaf_boxes, n, f_nl,
+                       (CellAux<double> *)ad, (CellAux<float> *)af);
+    return hipGetLastError();
 }
 
 hipError_t launch_voigt(int precision, int64_t n, const double *a, const double *x, double *out,

@@ -1,0 +1,104 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (default block and grid).
+
+The 64^3 dusty sphere runs its full 1e6-photon job on the GPU; the oracle
+recomputes sampled photons one by one (the first, middle and last ids) and
+their histories must match.  The full jobs in FP32-bulk and FP64 agree
+statistically.  The 128^3 halo and the ~2e6-leaf octree run on their full
+grids with a per-photon event cap, so the oracle can follow the same photons
+to the same event.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats as sst
+
+import oracle
+from paper_1409_4480_amd import colt, inputs
+from tests import stats
+from tests.test_gpu_parity import FLIP, FLIP_LOCAL, compare_records, say
+
+FLIP_DENSE = 0.25     # long histories in tau ~ 3e7 cells with local core-skipping
+
+pytestmark = pytest.mark.gpu
+
+PC = inputs.PC
+
+
+def sample_ids(n, k=1000):
+    return [(0, 2 * k), (n // 2, n // 2 + k), (n - k, n)]
+
+
+@pytest.fixture(scope="module")
+def dusty_full():
+    wl = inputs.dusty_sphere()                      # 64^3, tau0 = 1e7, 1e6 photons
+    say("[gpu] dusty sphere 64^3, 1e6 photons, FP64 with records")
+    g64 = colt.run(wl, precision=colt.FP64, record=True)
+    say("[gpu] dusty sphere 64^3, 1e6 photons, FP32-bulk")
+    g32 = colt.run(wl, precision=colt.FP32_BULK, record=True)
+    return wl, g64, g32
+
+
+def test_dusty_sphere_full_size_fp64_sampled_histories(dusty_full):
+    wl, g64, _ = dusty_full
+    n = wl["params"]["n_photons"]
+    for lo, hi in sample_ids(n):
+        r = oracle.run(wl["grid"], wl["source"], wl["params"], id_begin=lo, id_end=hi,
+                       records=True)
+        compare_records(g64, r, 2 * PC, lo=lo, hi=hi, flip=FLIP)
+    c = g64["counters"]
+    assert c["emitted"] == n == c["escaped"] + c["absorbed"]
+    assert g64["spectrum"].sum() == c["escaped"]
+
+
+def test_dusty_sphere_full_size_fp32_matches_fp64(dusty_full):
+    wl, g64, g32 = dusty_full
+    n = wl["params"]["n_photons"]
+    c32, c64 = g32["counters"], g64["counters"]
+    assert c32["emitted"] == n == c32["escaped"] + c32["absorbed"]
+    f32, f64 = c32["escaped"] / n, c64["escaped"] / n
+    se = math.sqrt((f32 * (1 - f32) + f64 * (1 - f64)) / n)
+    assert abs(f32 - f64) < 3 * se
+    assert stats.chi2_two_hist_p(g32["spectrum"], g64["spectrum"]) > 0.01
+    x32 = g32["records"]["x"][g32["records"]["status"] == 1]
+    x64 = g64["records"]["x"][g64["records"]["status"] == 1]
+    assert sst.ks_2samp(x32, x64).pvalue > 0.01
+    n32, n64 = g32["records"]["nscat"], g64["records"]["nscat"]
+    se = math.sqrt((n32.var() + n64.var()) / n)
+    assert abs(n32.mean() - n64.mean()) < 3 * se
+
+
+def test_halo_full_grid_capped_histories():
+    """128^3 halo with cone, wind and eight 256^2 cameras; 256 photons followed
+    to 3000 events each.  Central cells have tau ~ 3e7 and local core-skipping
+    makes x_crit depend on the distance to the nearest face, which rounding
+    fixes only to ~1e-14 of a cell; with mean free paths of ~1e-7 cell that
+    perturbs x at the 1e-7 level, so a larger share of long histories flips a
+    branch here (FLIP_DENSE).  The outcome distributions must still agree."""
+    n, cap = 256, 3000
+    wl = inputs.halo(n_photons=n)
+    wl["params"]["max_events"] = cap
+    say(f"[gpu] halo 128^3, {n} photons, cap {cap} events")
+    g = colt.run(wl, precision=colt.FP64, record=True, max_events=cap)
+    r = oracle.run(wl["grid"], wl["source"], wl["params"], records=True)
+    compare_records(g, r, 200 * PC, peel=True, flip=FLIP_DENSE)
+    c = g["counters"]
+    assert c["capped"] + c["escaped"] == n
+    assert abs(c["escaped"] - r["counters"]["escaped"]) <= max(3, 0.1 * n)
+    rg = np.linalg.norm(g["records"]["pos"], axis=1)
+    rr = np.linalg.norm(r["records"]["pos"], axis=1)
+    assert sst.ks_2samp(rg, rr).pvalue > 0.01
+    assert sst.ks_2samp(g["records"]["x"], r["records"]["x"]).pvalue > 0.01
+
+
+def test_octree_full_size_capped_histories():
+    """~2e6-leaf NFW octree (64^3 base + 4 levels), 64 sources, 4 cameras of
+    512^2 pixels; 64 photons followed to 5000 events each."""
+    wl = inputs.nfw_octree(n_photons=64)
+    assert 1.9e6 <= wl["leaves"] <= 2.1e6
+    wl["params"]["max_events"] = 5_000
+    say(f"[gpu] NFW octree {wl['leaves']} leaves, 64 photons, cap 5000 events")
+    g = colt.run(wl, precision=colt.FP64, record=True, max_events=5_000)
+    r = oracle.run(wl["grid"], wl["source"], wl["params"], records=True)
+    compare_records(g, r, 4000 * PC, peel=True, flip=FLIP_LOCAL)
