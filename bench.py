@@ -74,6 +74,45 @@ def cpu_baseline(n_photons_full, budget_s=15.0):
             "photons_per_s": n / dt}
 
 
+def serve_section(n_jobs):
+    """Serving stream of uneven spheres (grid 32^3-64^3, tau0 1e4-1e5,
+    1e4-5e4 photons, half with Hubble-like outflows): capacity with every job
+    arrived at once, then Poisson arrivals at 0.8 of that capacity with p50/p99
+    latency, against one job at a time in plain FP64."""
+    import numpy as np
+    import torch
+
+    from paper_1409_4480_amd import colt, inputs, serving
+
+    stream = inputs.job_stream(n_jobs=n_jobs, seed=5, n_range=(32, 64),
+                               tau_range=(1.0e4, 1.0e5), ph_range=(1.0e4, 5.0e4))
+    srv = serving.Server(epoch_photons=1 << 20, min_quota=8192)
+    out = srv.run(stream, realtime=False)
+    batched = serving.summarize(out, srv.makespan)
+    rate = 0.8 * n_jobs / srv.makespan
+    rng = np.random.default_rng(5)
+    t = 0.0
+    for wl in stream:
+        t += rng.exponential(1.0 / rate)
+        wl["arrival"] = t
+    srv = serving.Server(epoch_photons=1 << 20, min_quota=8192)
+    out = srv.run(stream, realtime=True)
+    poisson = serving.summarize(out, srv.makespan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    scat = 0
+    for wl in stream:
+        r = colt.run(wl, precision=colt.FP64)
+        scat += r["counters"]["scat_hi"]
+    serial = time.perf_counter() - t0
+    return {"config": {"jobs": n_jobs, "grid": "32^3-64^3", "tau0": "1e4-1e5",
+                       "photons": "1e4-5e4", "precision": "FP32-bulk", "epoch_photons": 1 << 20},
+            "batched": batched,
+            "poisson": dict(poisson, rate_jobs_per_s=rate),
+            "serial_fp64": {"scatterings_per_s": scat / serial, "makespan_s": serial},
+            "speedup_batched_vs_serial_fp64": batched["scatterings_per_s"] / (scat / serial)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +123,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--serve-jobs", type=int, default=48,
+                    help="jobs in the serving stream (0 skips the serving section)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -159,7 +200,12 @@ def main():
         "per_step": {"scatterings": scat / args.steps,
                      "escaped_fraction": sum(c["escaped"] for c in cnt) / photons,
                      "upar_tries_per_scattering": sum(c["upar_tries"] for c in cnt) / max(scat, 1),
-                     "crossings": sum(c["crossings"] for c in cnt) / args.steps},
+                     "crossings": sum(c["crossings"] for c in cnt) / args.steps,
+                     "loop_passes": sum(c["passes"] for c in cnt) / args.steps,
+                     "upar_rounds_per_pass": sum(c["upar_rounds"] for c in cnt) /
+                     max(sum(c["passes"] for c in cnt), 1),
+                     "upar_candidate_lane_use": sum(c["upar_tries"] for c in cnt) /
+                     max(64 * sum(c["upar_rounds"] for c in cnt), 1)},
         "grid_setup_ms": grid_setup_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": None,
@@ -178,6 +224,13 @@ def main():
             sum(c["emitted"] for c in cnt64)}
         result["speedup_mixed_vs_fp64"] = value / (scat64 / el64)
     grid.release()
+    if args.serve_jobs > 0:
+        result["serving"] = serve_section(args.serve_jobs)
+        result["latency_ms"] = {"p50": result["serving"]["poisson"]["p50_ms"],
+                                "p99": result["serving"]["poisson"]["p99_ms"],
+                                "of": "serving stream jobs (arrival to tallies on host)"}
+        result["per_step"]["step_latency_ms"] = {"p50": float(np.percentile(lat, 50)),
+                                                 "p99": float(np.percentile(lat, 99))}
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(args.photons)
     print(json.dumps(result), flush=True)

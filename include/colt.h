@@ -70,6 +70,7 @@ typedef int32_t colt_status;
 
 typedef struct colt_grid_s *colt_grid;
 typedef struct colt_job_s *colt_job;
+typedef struct colt_graph_s *colt_graph;
 
 /* Device allocator (e.g. a framework's caching allocator).  alloc returns a
  * device pointer of at least `bytes` bytes, 256-byte aligned, or NULL. */
@@ -202,6 +203,21 @@ colt_status colt_emit(colt_grid grid, const colt_source_desc *src,
  * COLT_ERR_HIP. */
 colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
                            void *stream);
+
+/* Captures one transport epoch over n_jobs jobs (one precision) into a HIP
+ * graph: a planning kernel takes up to photons_per_job photons (all if 0) from
+ * each job's device-side cursor, the persistent transport kernel runs them,
+ * and a second kernel advances the cursors.  Every colt_graph_launch replays
+ * one epoch, so repeated launches walk through the jobs without host work
+ * beyond the launch; replays after a job is complete do nothing for it.
+ * Capture needs a non-default stream.  The jobs must outlive the graph and
+ * must not be passed to colt_transport while the graph is in use.
+ * Errors: COLT_ERR_ARG, COLT_ERR_NOMEM, COLT_ERR_HIP. */
+colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
+                              void *capture_stream, colt_graph *out);
+/* Replays one epoch on `stream` (asynchronous). */
+colt_status colt_graph_launch(colt_graph graph, void *stream);
+void colt_graph_release(colt_graph graph);
 
 /* Copies a job's tallies to caller buffers (sizes from its params).  With
  * wait = 1 it first synchronises the job's last stream; with wait = 0 it

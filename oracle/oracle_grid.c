@@ -177,6 +177,12 @@ static double nonlocal_cell(const orc_grid *g, const orc_cell *c0, double f_nl)
             double p[3], k[3] = { 0.0, 0.0, 0.0 };
             k[d] = (double)s;
             for (int e = 0; e < 3; ++e) p[e] = 0.5 * (c0->lo[e] + c0->hi[e]);
+            if (g->kind == 1) {          /* octree: the centre as a lattice point */
+                const double unit = (g->box_max[0] - g->box_min[0]) /
+                                    (double)((int64_t)1 << ORC_OCT_DEPTH);
+                for (int e = 0; e < 3; ++e)
+                    p[e] = g->box_min[e] + (double)(c0->I[e] + c0->S / 2) * unit;
+            }
             p[d] = (s > 0) ? c0->hi[d] : c0->lo[d];
             double sum = 0.0;
             orc_cell c;

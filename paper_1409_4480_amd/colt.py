@@ -24,7 +24,8 @@ COUNTER_NAMES = ["emitted", "escaped", "absorbed", "scat_hi", "scat_dust", "cros
 EXPORTS = ["colt_init_grid", "colt_emit", "colt_transport", "colt_tally", "colt_job_status",
            "colt_grid_bytes", "colt_job_bytes", "colt_last_kernel_ms", "colt_release_job",
            "colt_release_grid", "colt_last_error", "colt_grid_fields", "colt_eval_voigt",
-           "colt_sample", "colt_grid_nonlocal"]
+           "colt_sample", "colt_grid_nonlocal", "colt_graph_create", "colt_graph_launch",
+           "colt_graph_release"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -113,13 +114,19 @@ def lib():
         L.colt_last_error.restype = ctypes.c_char_p
         L.colt_grid_fields.argtypes = [vp, _dp]
         L.colt_grid_nonlocal.argtypes = [vp, ctypes.c_double, vp]
+        L.colt_graph_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(Launch),
+                                        vp, ctypes.POINTER(vp)]
+        L.colt_graph_launch.argtypes = [vp, vp]
+        L.colt_graph_release.argtypes = [vp]
+        L.colt_graph_release.restype = None
         L.colt_eval_voigt.argtypes = [ctypes.c_int32, _dp, _dp, ctypes.c_int64, _dp, vp]
         L.colt_sample.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                                   ctypes.c_int64, _dp, _ip, vp]
         for name in ("colt_init_grid", "colt_emit", "colt_transport", "colt_tally",
                      "colt_job_status", "colt_release_grid", "colt_grid_fields",
-                     "colt_eval_voigt", "colt_sample", "colt_grid_nonlocal"):
+                     "colt_eval_voigt", "colt_sample", "colt_grid_nonlocal",
+                     "colt_graph_create", "colt_graph_launch"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -339,6 +346,33 @@ def transport(jobs, block=0, blocks_per_cu=0, photons_per_job=0, time_kernel=Fal
     lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), int(bool(time_kernel)))
     _check(lib().colt_transport(arr, len(jobs), ctypes.byref(lc),
                                 stream if stream is not None else current_stream()))
+
+
+class Graph:
+    """One transport epoch over fixed jobs captured as a HIP graph; each
+    launch() replays an epoch of up to photons_per_job photons per job."""
+
+    def __init__(self, jobs, photons_per_job=0, block=0, blocks_per_cu=0):
+        torch = _torch()
+        self.jobs = list(jobs)
+        self._capture = torch.cuda.Stream()
+        arr = (ctypes.c_void_p * len(self.jobs))(*[j.handle for j in self.jobs])
+        lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), 0)
+        h = ctypes.c_void_p()
+        torch.cuda.current_stream().synchronize()
+        _check(lib().colt_graph_create(arr, len(self.jobs), ctypes.byref(lc),
+                                       ctypes.c_void_p(self._capture.cuda_stream),
+                                       ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().colt_graph_launch(self.handle,
+                                       stream if stream is not None else current_stream()))
+
+    def release(self):
+        if self.handle:
+            lib().colt_graph_release(self.handle)
+            self.handle = None
 
 
 def last_kernel_ms():

@@ -142,6 +142,14 @@ struct colt_grid_s {
     hipStream_t stream = nullptr;
 };
 
+struct colt_graph_s {
+    std::vector<colt_job> jobs;
+    void *dev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t quota = 0;
+};
+
 struct colt_job_s {
     DevMem mem;
     colt_grid grid = nullptr;
@@ -656,13 +664,13 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
         L.first_id = (const uint64_t *)(dv + off_first);
         L.queue = (unsigned long long *)(dv + off_queue);
         L.n_jobs = nj;
-        L.total = prefix.back();
+        const uint64_t total = prefix.back();
         int per_cu = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 0;
         if (per_cu <= 0) {
             HIP_TRY(transport_occupancy(prec, cams, nj == 1, block, &per_cu));
             if (per_cu <= 0) per_cu = 1;
         }
-        const uint64_t lanes_needed = (L.total + 63) / 64 * 64;
+        const uint64_t lanes_needed = (total + 63) / 64 * 64;
         uint64_t grid = (uint64_t)cu_count() * per_cu;
         const uint64_t grid_needed = (lanes_needed + block - 1) / block;
         if (grid > grid_needed) grid = grid_needed;
@@ -688,6 +696,113 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
         }
     }
     return COLT_OK;
+}
+
+colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
+                              void *capture_stream, colt_graph *out)
+{
+    if (!out) return fail(COLT_ERR_ARG, "null output");
+    *out = nullptr;
+    if (n_jobs < 1 || !jobs) return fail(COLT_ERR_ARG, "a graph needs at least one job");
+    if (!capture_stream) return fail(COLT_ERR_ARG, "capture needs a non-default stream");
+    const int prec = jobs[0] ? jobs[0]->params.precision : 0;
+    bool cams = false;
+    for (int i = 0; i < n_jobs; ++i) {
+        if (!jobs[i]) return fail(COLT_ERR_ARG, "null job %d", i);
+        if (jobs[i]->params.precision != prec)
+            return fail(COLT_ERR_ARG, "all jobs of a graph share one precision");
+        for (int k = 0; k < i; ++k)
+            if (jobs[k] == jobs[i]) return fail(COLT_ERR_ARG, "job %d listed twice", i);
+        cams = cams || jobs[i]->params.n_cams > 0;
+    }
+    const int block = (launch && launch->block) ? launch->block : 256;
+    if (block < 64 || block > 256 || block % 64) return fail(COLT_ERR_ARG, "block 64..256");
+    int per_cu = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 0;
+    if (per_cu <= 0) {
+        HIP_TRY(transport_occupancy(prec, cams, n_jobs == 1, block, &per_cu));
+        if (per_cu <= 0) per_cu = 1;
+    }
+    const int nj = n_jobs;
+    const size_t off_n = ((sizeof(JobView) * nj) + 255) & ~size_t(255);
+    const size_t off_cur = off_n + ((8 * nj + 255) & ~size_t(255));
+    const size_t off_prefix = off_cur + ((8 * nj + 255) & ~size_t(255));
+    const size_t off_first = off_prefix + ((8 * (nj + 1) + 255) & ~size_t(255));
+    const size_t off_queue = off_first + ((8 * nj + 255) & ~size_t(255));
+    const size_t bytes = off_queue + 256;
+    std::vector<char> h(bytes, 0);
+    for (int i = 0; i < nj; ++i) {
+        std::memcpy(h.data() + i * sizeof(JobView), &jobs[i]->view, sizeof(JobView));
+        const uint64_t n = jobs[i]->params.n_photons, c = jobs[i]->launched;
+        std::memcpy(h.data() + off_n + 8 * i, &n, 8);
+        std::memcpy(h.data() + off_cur + 8 * i, &c, 8);
+    }
+    colt_graph gr = new colt_graph_s();
+    gr->jobs.assign(jobs, jobs + nj);
+    gr->quota = launch ? launch->photons_per_job : 0;
+    if (hipMalloc(&gr->dev, bytes) != hipSuccess) {
+        delete gr;
+        return fail(COLT_ERR_NOMEM, "graph tables allocation failed");
+    }
+    hipStream_t s = (hipStream_t)capture_stream;
+    hipError_t e = hipMemcpy(gr->dev, h.data(), bytes, hipMemcpyHostToDevice);
+    char *dv = (char *)gr->dev;
+    PlanView P{};
+    P.n_jobs = nj;
+    P.quota = gr->quota;
+    P.n_photons = (const uint64_t *)(dv + off_n);
+    P.cursor = (uint64_t *)(dv + off_cur);
+    P.prefix = (uint64_t *)(dv + off_prefix);
+    P.first_id = (uint64_t *)(dv + off_first);
+    P.queue = (unsigned long long *)(dv + off_queue);
+    LaunchView L{};
+    L.jobs = (const JobView *)dv;
+    L.prefix = P.prefix;
+    L.first_id = P.first_id;
+    L.queue = P.queue;
+    L.n_jobs = nj;
+    const int grid = cu_count() * per_cu;
+    if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = launch_plan(P, false, s);
+        if (e1 == hipSuccess) e1 = launch_transport(prec, cams, L, grid, block, s);
+        if (e1 == hipSuccess) e1 = launch_plan(P, true, s);
+        e = hipStreamEndCapture(s, &gr->graph);
+        if (e1 != hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        (void)hipFree(gr->dev);
+        delete gr;
+        return fail(COLT_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    *out = gr;
+    return COLT_OK;
+}
+
+colt_status colt_graph_launch(colt_graph gr, void *stream)
+{
+    if (!gr) return fail(COLT_ERR_ARG, "null graph");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipGraphLaunch(gr->exec, s));
+    for (colt_job j : gr->jobs) {        // host mirror of the device plan
+        const uint64_t left = j->params.n_photons - j->launched;
+        j->launched += (gr->quota && gr->quota < left) ? gr->quota : left;
+        HIP_TRY(hipEventRecord(j->done, s));
+        j->ever_launched = true;
+    }
+    return COLT_OK;
+}
+
+void colt_graph_release(colt_graph gr)
+{
+    if (!gr) return;
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(gr->dev);
+    delete gr;
 }
 
 double colt_last_kernel_ms(void)

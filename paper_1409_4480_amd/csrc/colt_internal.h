@@ -71,14 +71,27 @@ struct JobView {
 };
 
 // One persistent launch: jobs[j] takes global queue indices
-// [prefix[j], prefix[j+1]) as photon ids first_id[j] + (index - prefix[j]).
+// [prefix[j], prefix[j+1]) as photon ids first_id[j] + (index - prefix[j]);
+// prefix[n_jobs] is the number of photons of the launch.  The tables live in
+// device memory, so a captured graph can re-plan them on every replay.
 struct LaunchView {
     const JobView *jobs;
     const uint64_t *prefix;
     const uint64_t *first_id;
     unsigned long long *queue;
     int32_t n_jobs, pad;
-    uint64_t total;
+};
+
+// Device-side planning of a graph replay: each job takes up to `quota`
+// photons from its cursor; the cursors advance after the transport.
+struct PlanView {
+    int32_t n_jobs, pad;
+    uint64_t quota;
+    const uint64_t *n_photons;
+    uint64_t *cursor;
+    uint64_t *prefix;
+    uint64_t *first_id;
+    unsigned long long *queue;
 };
 
 }  // namespace colt

@@ -161,10 +161,16 @@ __device__ __forceinline__ double exit_distance(const GridView &g, const CellBox
             b += rc * k[d];
             rr += rc * rc;
         }
-        const double disc = b * b - (rr - g.esc_r * g.esc_r);
-        double t = (disc > 0.0) ? -b + ::sqrt(disc) : 0.0;
-        t = (t < 0.0) ? 0.0 : t;
-        if (t <= best) { best = t; by_sphere = true; }
+        // The sphere lies at least esc_r - |rc| away and the cell exit at most
+        // one cell diagonal (2 sizes bound it): skip the root when the sphere
+        // cannot be the nearer exit (the result is the same either way).
+        const double reach = g.esc_r - 2.0 * c.size;
+        if (reach <= 0.0 || rr >= reach * reach) {
+            const double disc = b * b - (rr - g.esc_r * g.esc_r);
+            double t = (disc > 0.0) ? -b + ::sqrt(disc) : 0.0;
+            t = (t < 0.0) ? 0.0 : t;
+            if (t <= best) { best = t; by_sphere = true; }
+        }
     }
     return best;
 }
@@ -276,13 +282,20 @@ struct Photon {
     Rng<R> rng;
 };
 
+// FP32-bulk takes 1/k from the single-precision reciprocal, as accurate as
+// the FP32 direction itself; FP64 divides exactly.
 template <typename R>
 __device__ __forceinline__ void set_dir(Photon<R> &p, R kx, R ky, R kz)
 {
     p.kr[0] = kx; p.kr[1] = ky; p.kr[2] = kz;
     p.k[0] = (double)kx; p.k[1] = (double)ky; p.k[2] = (double)kz;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) p.ik[d] = (p.k[d] != 0.0) ? 1.0 / p.k[d] : 0.0;
+    for (int d = 0; d < 3; ++d) {
+        if constexpr (sizeof(R) == 8)
+            p.ik[d] = (p.k[d] != 0.0) ? 1.0 / p.k[d] : 0.0;
+        else
+            p.ik[d] = (p.kr[d] != 0.0f) ? (double)__builtin_amdgcn_rcpf(p.kr[d]) : 0.0;
+    }
 }
 
 template <typename R>
@@ -724,7 +737,8 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
 #pragma unroll
     for (int i = 0; i < kLaneCounters; ++i) lc.v[i] = 0;
     const JobView *J = SINGLE ? L.jobs : nullptr;
-    bool have = false, drained = false;
+    const uint64_t total = L.prefix[L.n_jobs];
+    bool have = false, drained = total == 0;
     for (;;) {
         if (!drained) {
             const uint64_t need = __ballot(!have);
@@ -736,10 +750,10 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
                 const uint32_t blo = __shfl((uint32_t)base, leader);
                 const uint32_t bhi = __shfl((uint32_t)(base >> 32), leader);
                 base = ((unsigned long long)bhi << 32) | blo;
-                if (base + n_need >= L.total) drained = true;
+                if (base + n_need >= total) drained = true;
                 if (!have) {
                     const uint64_t g = base + __popcll(need & lane_lt);
-                    if (g < L.total) {
+                    if (g < total) {
                         uint64_t id;
                         if constexpr (SINGLE) {
                             id = L.first_id[0] + g;
@@ -808,6 +822,31 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
         }
     }
     if (SINGLE || J) flush_counters(J, lc, slot);
+}
+
+// ---------------------------------------------------------------------------
+// Graph replays: plan the next slice of every job from device cursors, and
+// advance the cursors after the transport (no host data in the replay).
+// ---------------------------------------------------------------------------
+__global__ void k_plan(PlanView P)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t acc = 0;
+    P.prefix[0] = 0;
+    for (int j = 0; j < P.n_jobs; ++j) {
+        const uint64_t left = P.n_photons[j] - P.cursor[j];
+        const uint64_t take = (P.quota && P.quota < left) ? P.quota : left;
+        P.first_id[j] = P.cursor[j];
+        acc += take;
+        P.prefix[j + 1] = acc;
+    }
+    *P.queue = 0ull;
+}
+
+__global__ void k_advance(PlanView P)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int j = 0; j < P.n_jobs; ++j) P.cursor[j] += P.prefix[j + 1] - P.prefix[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -994,6 +1033,13 @@ hipError_t transport_occupancy(int precision, bool cams, bool single, int block,
                             : occupancy_t<float, true, false>(block, blocks_per_cu);
     return single ? occupancy_t<float, false, true>(block, blocks_per_cu)
                   : occupancy_t<float, false, false>(block, blocks_per_cu);
+}
+
+hipError_t launch_plan(const PlanView &P, bool advance, hipStream_t s)
+{
+    if (advance) hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, P);
+    else hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, s, P);
+    return hipGetLastError();
 }
 
 hipError_t launch_nonlocal(const GridView &g, const double *n_HI, const double *leaf_boxes,

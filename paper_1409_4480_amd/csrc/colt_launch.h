@@ -15,6 +15,7 @@ hipError_t launch_transport(int precision, bool cams, const LaunchView &L, int g
                             hipStream_t s);
 hipError_t transport_occupancy(int precision, bool cams, bool single, int block,
                                int *blocks_per_cu);
+hipError_t launch_plan(const PlanView &P, bool advance, hipStream_t s);
 hipError_t launch_nonlocal(const GridView &g, const double *n_HI, const double *leaf_boxes,
                            int64_t n, double f_nl, void *ad, void *af, hipStream_t s);
 hipError_t launch_voigt(int precision, int64_t n, const double *a, const double *x, double *out,

@@ -97,6 +97,34 @@ def static_sphere(n=16, tau0=1.0e4, T=1.0e4, radius=PC, n_photons=2000,
             "params": params}
 
 
+def slab(tau0=1.0e7, T=1.0e4, half_thickness=PC, n_xy=64, n_photons=10_000,
+         seed=1409448010, n_bins=400, x_range=(-80.0, 80.0), xcrit_mode=1, cameras=None,
+         cam_npix=16):
+    """Static uniform slab of line-centre optical depth tau0 from the mid-plane
+    to each face (the test of Sec. 4.1): two cells across the thickness and
+    n_xy cells across each horizontal direction (box n_xy/2 times wider than
+    thick), central point source at x = 0, no recoil, global core-skipping."""
+    Z = half_thickness
+    n_HI = tau0 / (_sigma0(T) * Z)
+    box_min = np.array([-n_xy * Z / 2, -n_xy * Z / 2, -Z])
+    box_max = -box_min
+    n_cells = n_xy * n_xy * 2
+    grid = {"kind": 0, "shape": (n_xy, n_xy, 2), "box_min": box_min, "box_max": box_max,
+            "n_HI": np.full(n_cells, n_HI), "T": np.full(n_cells, float(T)), "v": None,
+            "k_dust": None, "albedo": 0.0, "escape_radius": 0.0}
+    atau0 = A_1E4 / np.sqrt(T / 1.0e4) * tau0
+    params = {"n_photons": int(n_photons), "seed": int(seed), "xcrit_mode": int(xcrit_mode),
+              "atau0": float(atau0), "recoil": 0, "isotropic": 0, "n_bins": int(n_bins),
+              "x_min": float(x_range[0]), "x_max": float(x_range[1]), "tau_peel_max": 50.0}
+    if cameras is not None:
+        params.update({"cam_dir": np.asarray(cameras, float).reshape(-1, 3),
+                       "cam_nbins": int(n_bins), "cam_xmin": float(x_range[0]),
+                       "cam_xmax": float(x_range[1]), "cam_npix": int(cam_npix),
+                       "cam_fov": float(box_max[0] - box_min[0])})
+    return {"name": f"slab_tau{tau0:g}", "grid": grid, "source":
+            {"kind": 0, "pos": np.zeros((1, 3)), "freq_mode": 0}, "params": params}
+
+
 def dusty_sphere(n=64, tau0=1.0e7, n_photons=1_000_000, seed=1409448002, n_bins=500,
                  tau_dust=1.0, albedo=0.32, radius=PC, **kw):
     """Sphere of tau0 = 1e7 with grey dust of optical depth tau_dust over the
@@ -111,10 +139,11 @@ def dusty_sphere(n=64, tau0=1.0e7, n_photons=1_000_000, seed=1409448002, n_bins=
 
 def halo(n=128, L=200.0 * PC, n_photons=10_000_000, seed=1409448003, n_cams=8,
          npix=256, n_bins=1000, v_wind=200.0, r_wind=100.0 * PC, n_max=1.0e2,
-         n_floor=1.0e-2, cone_deg=45.0, x_HI_cone=1.0e-4):
+         n_floor=1.0e-2, cone_deg=45.0, x_HI_cone=1.0e-4, f_nl=0.5):
     """Idealised first-galaxy halo: n_HI = n_max min(1, (r/dx)^-2) floored at
     n_floor; cells within cone_deg of the +-z axis are ionised (n_HI times
-    x_HI_cone); radial outflow rising linearly to v_wind at r_wind."""
+    x_HI_cone); radial outflow rising linearly to v_wind at r_wind.  Local
+    core-skipping with the non-local density threshold f_nl (Sec. 3.2.4)."""
     box_min = np.array([-L / 2] * 3)
     box_max = np.array([L / 2] * 3)
     dx = L / n
@@ -131,7 +160,7 @@ def halo(n=128, L=200.0 * PC, n_photons=10_000_000, seed=1409448003, n_cams=8,
     v = (unit * vr[..., None]).reshape(-1, 3)
     grid = {"kind": 0, "shape": (n, n, n), "box_min": box_min, "box_max": box_max,
             "n_HI": nh.reshape(-1), "T": np.full(n ** 3, 1.0e4), "v": v, "k_dust": None,
-            "albedo": 0.0, "escape_radius": 0.0}
+            "albedo": 0.0, "escape_radius": 0.0, "f_nl": float(f_nl)}
     cams = np.vstack([AXIS_CAMERAS, [1, 1, 1], [1, -1, 0]])[:n_cams].astype(float)
     cams /= np.linalg.norm(cams, axis=1, keepdims=True)
     xlo, xhi = velocity_window(1000.0)
@@ -230,12 +259,14 @@ def build_octree(box_min, size, base_level, max_extra, refine, max_nodes=None):
 def nfw_octree(L=4.0 * KPC, base_level=6, max_extra=4, r_vir=600.0 * PC, conc=5.0,
                tau0_max=1.0e8, leaves_target=(1.9e6, 2.1e6), turb_n=256, turb_rms=20.0,
                hubble=2139.6, n_src=64, n_photons=10_000_000, seed=1409448004,
-               n_bins=1000, npix=512, turb_seed=4480, src_seed=4481, r_floor=1.95 * PC):
+               n_bins=1000, npix=512, turb_seed=4480, src_seed=4481, r_floor=1.95 * PC,
+               f_nl=0.5):
     """Synthetic cosmological halo on an octree (stand-in for the simulated
     first galaxy of Sec. 5.2): NFW n_H with concentration `conc`, refined on
     n_H * width^3 until the leaf count lies in `leaves_target`; turbulent
     velocity (k^-11/3, rms turb_rms per component) plus Hubble flow `hubble`
-    km/s/Mpc; n_src sources uniform within the scale radius."""
+    km/s/Mpc; n_src sources uniform within the scale radius; local
+    core-skipping with the non-local density threshold f_nl (Sec. 3.2.4)."""
     r_s = r_vir / conc
     box_min = np.array([-L / 2] * 3)
 
@@ -289,7 +320,7 @@ def nfw_octree(L=4.0 * KPC, base_level=6, max_extra=4, r_vir=600.0 * PC, conc=5.
     src = dirs * (r_s * rng.random(n_src) ** (1.0 / 3.0))[:, None]
     grid = {"kind": 1, "box_min": box_min, "box_max": box_min + L, "child": child,
             "n_HI": n_HI, "T": np.full(len(child), 1.0e4), "v": v, "k_dust": None,
-            "albedo": 0.0, "escape_radius": 0.0, "level": level}
+            "albedo": 0.0, "escape_radius": 0.0, "level": level, "f_nl": float(f_nl)}
     cams = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1]], float)
     cams /= np.linalg.norm(cams, axis=1, keepdims=True)
     xlo, xhi = velocity_window(1000.0)

@@ -1,0 +1,138 @@
+"""Continuous-batching server for transfer jobs on one GPU.
+
+Jobs (workload dictionaries from ``inputs``, each with an arrival time in
+seconds) are admitted in arrival order while their device footprint fits the
+memory budget; every admitted job keeps its grid and tallies resident.  The
+server then runs epochs: one persistent transport launch over the next slice
+of photons of every active job (``colt_transport`` with ``photons_per_job``),
+so jobs that arrive while others are running join at the next epoch boundary
+and share the device with them.  A job's latency runs from its arrival to its
+tallies being on the host.
+
+Scheduling only: all transport work happens in the HIP library.
+"""
+import time
+from collections import deque
+
+import numpy as np
+
+from . import colt
+
+CELL_BYTES = 64 + 32 + 16 + 8 + 8      # FP64 + FP32 records, aux (both), n_HI
+
+
+def footprint(wl, record=False):
+    """Device bytes a job will hold (grid records plus tallies and records)."""
+    g, p = wl["grid"], wl["params"]
+    n_cells = int(np.asarray(g["n_HI"]).size)
+    n = CELL_BYTES * n_cells + 8 * (int(p.get("n_bins", 0)) + 2)
+    cams = p.get("cam_dir")
+    n_cams = 0 if cams is None else np.asarray(cams).size // 3
+    n += 8 * n_cams * (int(p.get("cam_nbins", 0)) + int(p.get("cam_npix", 0)) ** 2)
+    if g.get("child") is not None:
+        n += 4 * n_cells + 4 * 128 ** 3
+    if record:
+        n += 32 * int(p["n_photons"]) * (1 + n_cams)
+    return n + (64 << 10)
+
+
+class _Active:
+    __slots__ = ("wl", "grid", "job", "arrival", "admitted", "bytes", "index")
+
+
+class Server:
+    """Admits jobs by HBM footprint and runs them in shared epochs.
+
+    budget_bytes    device memory the server may hold (None: 90 % of free HBM)
+    epoch_photons   photons per epoch, split evenly over the active jobs
+    min_quota       smallest per-job slice of an epoch
+    """
+
+    def __init__(self, budget_bytes=None, epoch_photons=1 << 20, min_quota=8192,
+                 precision=colt.FP32_BULK, record=False, block=0, blocks_per_cu=0):
+        import torch
+        if budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info()
+            budget_bytes = int(0.9 * free)
+        self.budget = int(budget_bytes)
+        self.epoch_photons = int(epoch_photons)
+        self.min_quota = int(min_quota)
+        self.precision = precision
+        self.record = record
+        self.block = block
+        self.blocks_per_cu = blocks_per_cu
+        self._sync = torch.cuda.current_stream().synchronize
+
+    def run(self, workloads, realtime=True):
+        """Serves the jobs; returns one result dict per job, in input order.
+
+        With realtime=False every job is taken as arrived at time 0.
+        """
+        order = sorted(range(len(workloads)),
+                       key=lambda i: workloads[i].get("arrival", 0.0) if realtime else 0.0)
+        pending = deque(order)
+        for i in order:
+            if footprint(workloads[i], self.record) > self.budget:
+                raise colt.ColtError(f"job {i} needs more than the memory budget")
+        results = [None] * len(workloads)
+        active = []
+        used = 0
+        epochs = 0
+        self.max_active = 0
+        self.max_used = 0
+        t0 = time.perf_counter()
+        while pending or active:
+            now = time.perf_counter() - t0
+            while pending:
+                i = pending[0]
+                wl = workloads[i]
+                arrival = wl.get("arrival", 0.0) if realtime else 0.0
+                need = footprint(wl, self.record)
+                if arrival > now or used + need > self.budget:
+                    break
+                pending.popleft()
+                a = _Active()
+                a.wl, a.arrival, a.admitted, a.bytes, a.index = wl, arrival, now, need, i
+                a.grid = colt.Grid(wl["grid"])
+                a.job = colt.Job(a.grid, wl["source"], wl["params"], precision=self.precision,
+                                 record=self.record)
+                used += need
+                self.max_used = max(self.max_used, used)
+                active.append(a)
+            if not active:
+                nxt = workloads[pending[0]].get("arrival", 0.0)
+                time.sleep(max(0.0, min(nxt - (time.perf_counter() - t0), 0.05)))
+                continue
+            self.max_active = max(self.max_active, len(active))
+            quota = max(self.min_quota, self.epoch_photons // len(active))
+            colt.transport([a.job for a in active], photons_per_job=quota, block=self.block,
+                           blocks_per_cu=self.blocks_per_cu)
+            self._sync()
+            epochs += 1
+            still = []
+            for a in active:
+                launched, total = a.job.status()
+                if launched < total:
+                    still.append(a)
+                    continue
+                out = a.job.tally(wait=True)
+                done = time.perf_counter() - t0
+                out["latency_s"] = done - a.arrival
+                out["queue_s"] = a.admitted - a.arrival
+                out["finished_s"] = done
+                results[a.index] = out
+                a.job.release()
+                a.grid.release()
+                used -= a.bytes
+            active = still
+        self.epochs = epochs
+        self.makespan = time.perf_counter() - t0
+        return results
+
+
+def summarize(results, makespan):
+    lat = np.array([r["latency_s"] for r in results])
+    scat = sum(r["counters"]["scat_hi"] for r in results)
+    return {"jobs": len(results), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "makespan_s": makespan,
+            "scatterings": scat, "scatterings_per_s": scat / makespan}

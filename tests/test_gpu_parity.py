@@ -37,12 +37,21 @@ def say(msg):
     sys.stdout.flush()
 
 
+def oracle_grid(grid):
+    """The grid as the oracle sees it: a non-local threshold f_nl is turned
+    into the oracle's own per-cell estimate."""
+    f_nl = float(grid.get("f_nl", 0.0))
+    if f_nl > 0.0 and grid.get("atau_nl") is None:
+        grid = dict(grid, atau_nl=oracle.nonlocal_atau(grid, f_nl))
+    return grid
+
+
 def run_both(wl, precision=colt.FP64, id_range=None, **kw):
     say(f"[gpu] {wl.get('name', '?')} precision={precision} n={wl['params']['n_photons']}")
     g = colt.run(wl, precision=precision, record=True, **kw)
     lo, hi = id_range if id_range else (0, wl["params"]["n_photons"])
-    r = oracle.run(wl["grid"], wl["source"], wl["params"], id_begin=lo, id_end=hi,
-                   records=True)
+    r = oracle.run(oracle_grid(wl["grid"]), wl["source"], wl["params"], id_begin=lo,
+                   id_end=hi, records=True)
     return g, r
 
 
@@ -198,7 +207,7 @@ def test_halo_cameras_local_core_skip_parity():
     core-skipping and eight cameras, on a 32^3 grid (central density lowered
     to 0.03 cm^-3 so the oracle finishes in about a second)."""
     wl = inputs.halo(n=32, n_photons=300, npix=16, n_bins=200, seed=33, n_max=0.03,
-                     n_floor=1e-4)
+                     n_floor=1e-4, f_nl=0.0)
     g, r = run_both(wl)
     compare_records(g, r, 200 * PC, peel=True, flip=FLIP_LOCAL)
     statistically_equal(g, r, 300)
@@ -219,6 +228,31 @@ def test_octree_nfw_parity():
     for i in range(gp.shape[1]):
         se = math.sqrt((gp[:, i].var() + rp[:, i].var()) / gp.shape[0]) + 1e-300
         assert abs(gp[:, i].mean() - rp[:, i].mean()) < 3 * se
+
+
+def test_nonlocal_estimate_matches_oracle():
+    """Device non-local a*tau (Sec. 3.2.4) against the oracle, Cartesian halo
+    and NFW octree (per leaf)."""
+    for wl in (inputs.halo(n=32, n_photons=1),
+               inputs.nfw_octree(base_level=3, max_extra=2, leaves_target=(2500, 3500),
+                                 turb_n=16, n_photons=1)):
+        g = colt.Grid(wl["grid"])          # computes the estimate for f_nl = 0.5
+        f = g.fields()
+        g.release()
+        ref = oracle.nonlocal_atau(wl["grid"], 0.5)
+        if wl["grid"]["kind"] == 1:
+            ref = ref[np.asarray(wl["grid"]["child"]) < 0]
+        assert ref.max() > 1.0
+        assert np.allclose(f[:, 9], ref, rtol=1e-11, atol=1e-14)
+
+
+def test_halo_nonlocal_core_skip_parity():
+    """Denser halo (n_max = 0.3 cm^-3) with local + non-local core-skipping."""
+    wl = inputs.halo(n=32, n_photons=200, npix=16, n_bins=200, seed=35, n_max=0.3,
+                     n_floor=1e-4)
+    g, r = run_both(wl)
+    compare_records(g, r, 200 * PC, peel=True, flip=FLIP_LOCAL)
+    statistically_equal(g, r, 200)
 
 
 def test_octree_and_cartesian_agree_on_uniform_gas():

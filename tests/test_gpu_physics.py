@@ -1,0 +1,56 @@
+"""The paper's own validation problems (Sec. 4), run on the GPU at sizes the
+oracle would take minutes for: the static slab against the analytic spectrum
+at tau0 = 1e8 (eq. neufeld; the paper reports ~5 % maximum difference there),
+and the Hubble-expanding sphere, whose blue peak disappears by v_max ~ 200
+km/s (Sec. 4.2)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1409_4480_amd import colt, inputs
+from tests import stats
+from tests.test_gpu_parity import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", [colt.FP32_BULK, colt.FP64])
+def test_neufeld_slab_tau0_1e8(precision):
+    n = 200_000
+    w = inputs.slab(tau0=1e8, n_photons=n, seed=4108, n_bins=240, x_range=(-120, 120))
+    say(f"[gpu] slab tau0 1e8, {n} photons, precision {precision}")
+    out = colt.run(w, precision=precision, record=True)
+    x = out["records"]["x"]
+    assert out["counters"]["escaped"] == n
+    atau0 = 4.702e-4 * 1e8
+    grid = np.linspace(-200, 200, 400001)
+    J = stats.slab_J(grid, atau0)
+    ref_mean = np.trapezoid(np.abs(grid) * J, grid) / np.trapezoid(J, grid)
+    assert abs(np.abs(x).mean() / ref_mean - 1) < 0.03
+    # binned spectrum against the analytic J near the peaks (within ~5 %)
+    edges = np.linspace(-120, 120, 241)
+    h, _ = np.histogram(x, edges)
+    centre = 0.5 * (edges[1:] + edges[:-1])
+    Jb = stats.slab_J(centre, atau0)
+    model = Jb / Jb.sum() * n
+    peak = model > 0.5 * model.max()
+    dev = np.abs(h[peak] - model[peak]) / model.max()
+    assert dev.max() < 0.08
+    assert abs((x > 0).mean() - 0.5) < 4 * math.sqrt(0.25 / n)
+
+
+def test_expanding_sphere_loses_its_blue_peak():
+    """Uniform sphere of column N_HI = 2e20 cm^-2 at 1e4 K (tau0 = 1.18e7)."""
+    tau0 = 2e20 * 5.898e-14
+    frac = {}
+    for vmax in (0.0, 20.0, 200.0):
+        w = inputs.static_sphere(n=32, tau0=tau0, n_photons=40_000, seed=4200, isotropic=False,
+                                 xcrit_mode=1, v_max=vmax, n_bins=300, x_range=(-150, 150))
+        say(f"[gpu] expanding sphere v_max {vmax}")
+        out = colt.run(w, precision=colt.FP32_BULK, record=True)
+        x = out["records"]["x"]
+        frac[vmax] = (x > 0).mean()
+    assert abs(frac[0.0] - 0.5) < 0.02
+    assert frac[20.0] < 0.4
+    assert frac[200.0] < 0.02

@@ -370,3 +370,84 @@ def test_uniform_medium_trajectories_independent_of_grid(threads):
         same = (r["nscat"] == runs[0]["nscat"]) & (r["status"] == runs[0]["status"])
         assert same.mean() > 0.99
         assert np.allclose(r["x"][same], runs[0]["x"][same], atol=1e-6)
+
+
+# --------------------------------------------------------------------------- #
+# Non-local a*tau estimate (Sec. 3.2.4, eq. atauNL)                           #
+# --------------------------------------------------------------------------- #
+def test_nonlocal_estimate_uniform_sphere_closed_form():
+    """In a uniform sphere every path runs to the escape sphere, so the
+    estimate is a k0 times the shortest face-centre-to-sphere chord along the
+    six outward axes."""
+    n = 8
+    w = inputs.static_sphere(n=n, tau0=3e3)
+    g = w["grid"]
+    nl = oracle.nonlocal_atau(g, 0.5).reshape(n, n, n)
+    c = oracle.cell_constants(1e4, g["n_HI"][0])
+    R = PC
+    dx = 2 * R / n
+    worst = 0.0
+    for iz in range(n):
+        for iy in range(n):
+            for ix in range(n):
+                lo = -R + dx * np.array([ix, iy, iz])
+                centre = lo + dx / 2
+                best = np.inf
+                for d in range(3):
+                    for s in (1, -1):
+                        p = centre.copy()
+                        p[d] = lo[d] + (dx if s > 0 else 0.0)
+                        if p @ p >= R * R:
+                            t = 0.0
+                        else:
+                            t = -s * p[d] + math.sqrt(p[d] ** 2 - (p @ p - R * R))
+                        best = min(best, t)
+                ref = c["a"] * c["k0"] * best
+                assert abs(nl[iz, iy, ix] - ref) <= 1e-12 * max(ref, 1.0)
+                worst = max(worst, ref)
+    assert worst > 0.5
+    assert oracle.nonlocal_atau(g, 0.0).max() == 0.0
+
+
+def test_nonlocal_estimate_stops_at_density_jumps():
+    """Paths stop at the first cell whose density differs from the start by
+    f_NL or more: with a factor-10 jump at x = 8 cells, cells next to the
+    jump get 0 for f_NL = 1/2 and see across it for f_NL = 20."""
+    nx, ny = 16, 4
+    box = np.array([nx, ny, ny], float) * PC
+    dens = np.full((ny, ny, nx), 1.0)
+    dens[:, :, 8:] = 10.0
+    g = {"kind": 0, "shape": (nx, ny, ny), "box_min": np.zeros(3), "box_max": box,
+         "n_HI": dens.reshape(-1), "T": np.full(dens.size, 1e4)}
+    lo = oracle.nonlocal_atau(g, 0.5).reshape(ny, ny, nx)
+    hi = oracle.nonlocal_atau(g, 20.0).reshape(ny, ny, nx)
+    assert np.all(lo[:, :, 7] == 0.0) and np.all(lo[:, :, 8] == 0.0)
+    # an interior cell of the low-density side, two cells from the jump: its
+    # shortest path is 1 cell (to the y or z box face) on both thresholds
+    c1 = oracle.cell_constants(1e4, 1.0)
+    one_cell = c1["a"] * c1["k0"] * PC
+    assert abs(lo[1, 1, 5] / one_cell - 1) < 1e-12
+    assert hi[1, 1, 7] > 0.0 and abs(hi[1, 1, 7] / one_cell - 1) < 1e-12
+
+
+def test_neufeld_slab_spectrum(threads):
+    """The paper's static test (Sec. 4.1, eq. neufeld): a uniform slab with
+    tau0 = 1e7 at 1e4 K (a tau0 = 4702) emits the double-peaked spectrum
+    with peaks at +-1.06642 (a tau0)^(1/3); the paper reports agreement to
+    a few per cent at high tau0."""
+    w = inputs.slab(tau0=1e7, n_photons=4000, seed=77)
+    out = oracle.run(w["grid"], w["source"], w["params"], records=True, threads=threads)
+    x = out["records"]["x"]
+    atau0 = 4.702e-4 * 1e7
+    grid = np.linspace(-120, 120, 240001)
+    J = stats.slab_J(grid, atau0)
+    assert abs(grid[grid > 0][J[grid > 0].argmax()] / (1.06642 * atau0 ** (1 / 3)) - 1) < 1e-3
+    ref_mean = np.trapezoid(np.abs(grid) * J, grid) / np.trapezoid(J, grid)
+    assert abs(np.abs(x).mean() / ref_mean - 1) < 0.04
+    cdf = np.cumsum(J)
+    cdf /= cdf[-1]
+    assert abs(np.median(np.abs(x)) / grid[np.searchsorted(cdf, 0.75)] - 1) < 0.05
+    assert sst.ks_2samp(x, -x).pvalue > 0.01
+    # every photon leaves through the top or bottom face
+    z = np.abs(out["records"]["pos"][:, 2])
+    assert np.allclose(z, PC, rtol=1e-12)
