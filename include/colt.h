@@ -154,6 +154,11 @@ typedef struct {
                                           /* 0 = all that remain                   */
     int32_t time_kernel;                  /* 1: time the transport kernel with    */
                                           /* events (see colt_last_kernel_ms)      */
+    int32_t march_min;                    /* a wave keeps ray tracing while at     */
+                                          /* least this many of its 64 lanes are   */
+                                          /* in flight; 0 = default (16 FP32-bulk, */
+                                          /* 8 FP64), 1 = each                     */
+                                          /* flight ends within its pass           */
 } colt_launch;
 
 typedef struct {
@@ -259,7 +264,8 @@ colt_status colt_eval_voigt(int32_t precision, const double *a, const double *x,
  *   what 2: mu for W ~ 1 + p0 mu^2                    out[n]
  *   what 3: uniform numbers (k = 0 .. p0-1 of stream i) out[n*p0]
  *   what 4: as 0 with x_i = p1 + 0.41 (i mod 23) (-1)^i (mixed requests in a wave)
- *   what 5: as 0 with the one-lane sequential sampler */
+ *   what 5: as 0 with the one-lane sequential sampler
+ *   what 6: as 4 with the one-lane sequential sampler */
 colt_status colt_sample(int32_t what, int32_t precision, double p0, double p1, double p2,
                         uint64_t seed, int64_t n, double *out, int32_t *draws, void *stream);
 

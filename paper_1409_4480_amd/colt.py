@@ -70,7 +70,8 @@ class JobParams(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("photons_per_job", ctypes.c_uint64), ("time_kernel", ctypes.c_int32)]
+                ("photons_per_job", ctypes.c_uint64), ("time_kernel", ctypes.c_int32),
+                ("march_min", ctypes.c_int32)]
 
 
 class TallyOut(ctypes.Structure):
@@ -338,12 +339,13 @@ class Job:
 
 
 def transport(jobs, block=0, blocks_per_cu=0, photons_per_job=0, time_kernel=False,
-              stream=None):
+              stream=None, march_min=0):
     """Runs (the next slice of) each job's photons in one persistent launch per
     precision on the stream (asynchronous)."""
     jobs = list(jobs)
     arr = (ctypes.c_void_p * max(len(jobs), 1))(*[j.handle for j in jobs])
-    lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), int(bool(time_kernel)))
+    lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), int(bool(time_kernel)),
+                int(march_min))
     _check(lib().colt_transport(arr, len(jobs), ctypes.byref(lc),
                                 stream if stream is not None else current_stream()))
 
@@ -352,12 +354,12 @@ class Graph:
     """One transport epoch over fixed jobs captured as a HIP graph; each
     launch() replays an epoch of up to photons_per_job photons per job."""
 
-    def __init__(self, jobs, photons_per_job=0, block=0, blocks_per_cu=0):
+    def __init__(self, jobs, photons_per_job=0, block=0, blocks_per_cu=0, march_min=0):
         torch = _torch()
         self.jobs = list(jobs)
         self._capture = torch.cuda.Stream()
         arr = (ctypes.c_void_p * len(self.jobs))(*[j.handle for j in self.jobs])
-        lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), 0)
+        lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), 0, int(march_min))
         h = ctypes.c_void_p()
         torch.cuda.current_stream().synchronize()
         _check(lib().colt_graph_create(arr, len(self.jobs), ctypes.byref(lc),
@@ -391,25 +393,27 @@ def eval_voigt(a, x, precision=FP64):
 
 def sample(what, n, seed, p0=0.0, p1=0.0, p2=0.0, precision=FP64):
     """Device sampler draws (see colt_sample): 'upar', 'uperp', 'mu', 'uniform',
-    'upar_mixed', 'upar_seq'."""
-    code = {"upar": 0, "uperp": 1, "mu": 2, "uniform": 3, "upar_mixed": 4, "upar_seq": 5}[what]
+    'upar_mixed', 'upar_seq', 'upar_mixed_seq'."""
+    code = {"upar": 0, "uperp": 1, "mu": 2, "uniform": 3, "upar_mixed": 4, "upar_seq": 5,
+            "upar_mixed_seq": 6}[what]
     per = 2 if code == 1 else (int(p0) if code == 3 else 1)
     out = np.zeros(n * per)
     draws = np.zeros(n, np.int32)
     _check(lib().colt_sample(code, int(precision), float(p0), float(p1), float(p2), int(seed),
                              int(n), _ptr(out), _ptr(draws, _ip), current_stream()))
-    if code in (0, 4, 5):
+    if code in (0, 4, 5, 6):
         return out, draws
     return out.reshape(n, per) if per > 1 else out
 
 
-def run(workload, precision=FP64, record=False, block=0, blocks_per_cu=0, max_events=0):
+def run(workload, precision=FP64, record=False, block=0, blocks_per_cu=0, max_events=0,
+        march_min=0):
     """Initialises the grid, runs every photon of one job and returns its tallies."""
     g = Grid(workload["grid"])
     j = Job(g, workload["source"], workload["params"], precision=precision, record=record,
             max_events=max_events)
     try:
-        transport([j], block=block, blocks_per_cu=blocks_per_cu)
+        transport([j], block=block, blocks_per_cu=blocks_per_cu, march_min=march_min)
         return j.tally()
     finally:
         j.release()

@@ -611,6 +611,14 @@ void colt_release_job(colt_job j)
     delete j;
 }
 
+static int march_min_of(const colt_launch *launch, int precision)
+{
+    const int m = (launch && launch->march_min > 0)
+                      ? launch->march_min
+                      : ((precision == COLT_FP64) ? kDefaultMarchMinFp64 : kDefaultMarchMinFp32);
+    return m > 64 ? 64 : m;
+}
+
 colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
                            void *stream)
 {
@@ -664,6 +672,7 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
         L.first_id = (const uint64_t *)(dv + off_first);
         L.queue = (unsigned long long *)(dv + off_queue);
         L.n_jobs = nj;
+        L.march_min = march_min_of(launch, prec);
         const uint64_t total = prefix.back();
         int per_cu = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 0;
         if (per_cu <= 0) {
@@ -755,6 +764,7 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
     P.first_id = (uint64_t *)(dv + off_first);
     P.queue = (unsigned long long *)(dv + off_queue);
     LaunchView L{};
+    L.march_min = march_min_of(launch, prec);
     L.jobs = (const JobView *)dv;
     L.prefix = P.prefix;
     L.first_id = P.first_id;
@@ -885,8 +895,8 @@ colt_status colt_eval_voigt(int32_t precision, const double *a, const double *x,
 colt_status colt_sample(int32_t what, int32_t precision, double p0, double p1, double p2,
                         uint64_t seed, int64_t n, double *out, int32_t *draws, void *stream)
 {
-    const bool upar = what == 0 || what == 4 || what == 5;
-    if (what < 0 || what > 5 || n < 0 || (n > 0 && !out) || (upar && n > 0 && !draws))
+    const bool upar = what == 0 || what == 4 || what == 5 || what == 6;
+    if (what < 0 || what > 6 || n < 0 || (n > 0 && !out) || (upar && n > 0 && !draws))
         return fail(COLT_ERR_ARG, "bad sampler request");
     if (precision != 0 && precision != 1) return fail(COLT_ERR_ARG, "precision 0 or 1");
     if (what == 3 && !(p0 >= 1.0 && p0 <= 4096.0)) return fail(COLT_ERR_ARG, "1..4096 draws");

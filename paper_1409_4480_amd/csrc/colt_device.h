@@ -276,12 +276,59 @@ __device__ __forceinline__ UparReq<R> upar_setup(R a, R x, R xcw)
     return q;
 }
 
-// Uniform draws per candidate in stream units (advance of the draw index).
+// Advance of the draw index once candidate t (counted from 0) is accepted.
+// FP64: a core candidate takes one block (two draws), a two-part candidate
+// two blocks (four draws, the last unused).  FP32: two candidates share a
+// block (two words each) and the stream resumes at the next fresh block.
 template <typename R>
-__device__ __forceinline__ uint32_t upar_stride(int regime)
+__device__ __forceinline__ uint64_t upar_advance(int regime, uint32_t t)
 {
-    if constexpr (sizeof(R) == 8) return (regime == UPAR_SPLIT) ? 4u : 2u;
-    return 4u;
+    if constexpr (sizeof(R) == 8) return (uint64_t)((regime == UPAR_SPLIT) ? 4u : 2u) * (t + 1);
+    return 4ull * (t / 2 + 1);
+}
+
+// FP32 candidate from two words.  Core: theta = pi (R - 1/2) from the first,
+// acceptance draw from the second.  Two-part: the first word both picks the
+// part (probability p for the lower one) and, rescaled within the chosen
+// part's range of words, places theta in that part; the rescaled value is
+// uniform and independent of the choice.  The rescaling is done on the
+// integer word so that it keeps full precision however small either part's
+// share is.  The second word is the acceptance draw.
+__device__ __forceinline__ bool upar_eval_fp32(const UparReq<float> &q, uint32_t wa,
+                                               uint32_t wb, float &u)
+{
+    using F = Fn<float>;
+    float phi, bias = 0.0f;
+    if (q.regime == UPAR_CORE) {
+        phi = float(kPi) * u32f(wa);            // theta = pi (R - 1/2)
+    } else {
+        const uint32_t wp = (q.p >= 1.0f) ? 0xFFFFFFFFu : (uint32_t)(q.p * 4294967296.0f);
+        const bool lower = wa < wp;
+        const float Rth = F::div((float)(lower ? wa : wa - wp) + 0.5f,
+                                 (float)(lower ? wp : 0u - wp));
+        phi = lower ? Rth * q.th0 : q.th0 + Rth * (float(kPi) - q.th0);
+        if (!lower) bias = q.u0 * q.u0;
+    }
+    float c, s;
+    F::cossin2pi(phi * float(0.5 / kPi), c, s);
+    u = q.X - q.a * F::div(c, s);               // a tan(phi - pi/2) = -a cot(phi)
+    return u32f(wb) < F::exp(bias - u * u);
+}
+
+// FP32: both candidates 2b and 2b+1 of one block; returns whether either is
+// accepted, with the first accepted one in u and its position (0, 1) in half.
+__device__ __forceinline__ bool upar_pair_fp32(const UparReq<float> &q, const RngKey &key,
+                                               uint64_t B0, uint32_t b, float &u,
+                                               uint32_t &half)
+{
+    uint32_t w0, w1, w2, w3;
+    key.block(B0 + b, w0, w1, w2, w3);
+    float u0, u1;
+    const bool a0 = upar_eval_fp32(q, w0, w1, u0);
+    const bool a1 = upar_eval_fp32(q, w2, w3, u1);
+    u = a0 ? u0 : u1;
+    half = a0 ? 0u : 1u;
+    return a0 || a1;
 }
 
 // Candidate t of request q (unsigned |u|) from the photon's blocks starting at B0.
@@ -289,7 +336,6 @@ template <typename R>
 __device__ __forceinline__ bool upar_candidate(const UparReq<R> &q, const RngKey &key,
                                                uint64_t B0, uint32_t t, R &u)
 {
-    using F = Fn<R>;
     uint32_t w0, w1, w2, w3;
     if constexpr (sizeof(R) == 8) {
         if (q.regime == UPAR_CORE) {
@@ -314,24 +360,8 @@ __device__ __forceinline__ bool upar_candidate(const UparReq<R> &q, const RngKey
         }
         return Racc < acc;
     } else {
-        key.block(B0 + t, w0, w1, w2, w3);
-        float phi, uacc_bias = 0.0f;
-        bool lower = true;
-        float Racc;
-        if (q.regime == UPAR_CORE) {
-            phi = float(kPi) * u32f(w0);          // theta = pi (R - 1/2)
-            Racc = u32f(w1);
-        } else {
-            lower = u32f(w0) <= q.p;
-            const float Rth = u32f(w1);
-            phi = lower ? Rth * q.th0 : q.th0 + Rth * (float(kPi) - q.th0);
-            Racc = u32f(w2);
-            if (!lower) uacc_bias = q.u0 * q.u0;
-        }
-        float c, s;
-        F::cossin2pi(phi * float(0.5 / kPi), c, s);
-        u = q.X - q.a * F::div(c, s);              // a tan(phi - pi/2) = -a cot(phi)
-        return Racc < F::exp(uacc_bias - u * u);
+        key.block(B0 + t / 2, w0, w1, w2, w3);
+        return (t & 1) ? upar_eval_fp32(q, w2, w3, u) : upar_eval_fp32(q, w0, w1, u);
     }
 }
 
@@ -372,7 +402,7 @@ __device__ __forceinline__ R draw_upar(R a, R x, R xcw, Rng<R> &rng, uint32_t &t
     uint32_t t = 0;
     while (!upar_candidate<R>(q, rng.key, B0, t, u)) ++t;
     tries += t + 1;
-    rng.k += (uint64_t)upar_stride<R>(q.regime) * (t + 1);
+    rng.k += upar_advance<R>(q.regime, t);
     return sgn * u;
 }
 

@@ -12,6 +12,10 @@ constexpr double kVthRef = 12.85;          // km/s, thermal speed at 1e4 K (Sec.
 constexpr int kCounterSlots = 64;          // counter copies per job (spread atomics)
 constexpr int kNumCounters = 16;
 constexpr int kMaxCams = 64;
+// Lanes in flight that keep a wave ray tracing (measured best on the 64^3
+// dusty sphere: 16 of 64 in FP32-bulk, 8 in FP64).
+constexpr int kDefaultMarchMinFp32 = 16;
+constexpr int kDefaultMarchMinFp64 = 8;
 
 // Line data of one cell for the march: opacity at line centre per grid unit,
 // damping parameter, v_ref / v_th, dust opacity per grid unit, bulk velocity
@@ -79,7 +83,8 @@ struct LaunchView {
     const uint64_t *prefix;
     const uint64_t *first_id;
     unsigned long long *queue;
-    int32_t n_jobs, pad;
+    int32_t n_jobs;
+    int32_t march_min;          // a wave keeps stepping while this many lanes are in flight
 };
 
 // Device-side planning of a graph replay: each job takes up to `quota`

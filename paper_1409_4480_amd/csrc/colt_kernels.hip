@@ -17,6 +17,9 @@
 #ifndef COLT_FP32_MIN_BLOCKS
 #define COLT_FP32_MIN_BLOCKS 3
 #endif
+#ifndef COLT_FP64_MIN_BLOCKS
+#define COLT_FP64_MIN_BLOCKS 2
+#endif
 
 namespace colt {
 
@@ -245,56 +248,78 @@ __device__ __forceinline__ int bin_of(double x, double lo, double hi, int n)
     return 1 + (int)t;
 }
 
-// Per-lane event counters, flushed to the job's spread counter slots.
+// Per-lane event counters.  They live in LDS (64-bit, one column per lane of
+// the workgroup), so counting takes no registers and no wait: an event adds
+// to the lane's own column, and the column is flushed to the job's spread
+// counter slots when the lane changes job and at the end.
 constexpr int kLaneCounters = 12;
-struct LaneCounters {
-    uint32_t v[kLaneCounters];
-};
+constexpr int kMaxBlock = 256;
 
 // C_ROUNDS (cooperative sampler rounds) and C_PASSES (wave-loop passes) are
 // counted once per wave, by its first lane.
 enum { C_EMITTED = 0, C_ESCAPED, C_ABSORBED, C_SCAT_HI, C_SCAT_DUST, C_CROSSINGS, C_PEELS,
        C_UPAR_TRIES, C_PEEL_CROSSINGS, C_CAPPED, C_ROUNDS, C_PASSES };
 
+struct LaneCounters {
+    unsigned long long *col;     // &counts[0][threadIdx.x] in the workgroup's LDS table
+    __device__ __forceinline__ void add(int c, uint32_t by = 1u)
+    {
+        atomicAdd(col + c * kMaxBlock, (unsigned long long)by);
+    }
+};
+
 __device__ __forceinline__ void flush_counters(const JobView *J, LaneCounters &lc, int slot)
 {
     unsigned long long *dst = J->counters + (size_t)slot * kNumCounters;
 #pragma unroll
     for (int i = 0; i < kLaneCounters; ++i) {
-        if (lc.v[i]) atomicAdd(dst + i, (unsigned long long)lc.v[i]);
-        lc.v[i] = 0;
+        const unsigned long long v = lc.col[i * kMaxBlock];
+        if (v) atomicAdd(dst + i, v);
+        lc.col[i * kMaxBlock] = 0ull;
     }
 }
 
 template <typename R>
 struct Photon {
     double r[3];
-    double k[3];      // direction (double copy for geometry)
-    double ik[3];     // 1 / k
     R kr[3];          // direction in the bulk precision
+    double ik[3];     // FP64: 1 / k (FP32-bulk recomputes it where needed)
     R x;              // lab-frame frequency (Doppler widths at 1e4 K)
     double tau;       // optical depth left to the next interaction
     CellBox c;
-    uint64_t id;
     uint64_t events;
     int32_t nscat;
     int32_t status;   // 0 alive, 1 escaped, 2 absorbed, 3 capped
-    Rng<R> rng;
+    Rng<R> rng;       // its counter space also carries the photon id
+    __device__ __forceinline__ uint64_t id() const
+    {
+        return ((uint64_t)rng.key.id1 << 32) | rng.key.id0;
+    }
 };
 
-// FP32-bulk takes 1/k from the single-precision reciprocal, as accurate as
-// the FP32 direction itself; FP64 divides exactly.
 template <typename R>
 __device__ __forceinline__ void set_dir(Photon<R> &p, R kx, R ky, R kz)
 {
     p.kr[0] = kx; p.kr[1] = ky; p.kr[2] = kz;
-    p.k[0] = (double)kx; p.k[1] = (double)ky; p.k[2] = (double)kz;
+    if constexpr (sizeof(R) == 8) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) p.ik[d] = (p.kr[d] != 0.0) ? 1.0 / p.kr[d] : 0.0;
+    }
+}
+
+// Direction and its inverse for the geometry, in double.  FP32-bulk takes
+// 1/k from the single-precision reciprocal, as accurate as the FP32 direction
+// itself; FP64 uses the exact quotients kept with the photon.
+template <typename R>
+__device__ __forceinline__ void geom_dir(const Photon<R> &p, double k[3], double ik[3])
+{
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+        k[d] = (double)p.kr[d];
         if constexpr (sizeof(R) == 8)
-            p.ik[d] = (p.k[d] != 0.0) ? 1.0 / p.k[d] : 0.0;
+            ik[d] = p.ik[d];
         else
-            p.ik[d] = (p.kr[d] != 0.0f) ? (double)__builtin_amdgcn_rcpf(p.kr[d]) : 0.0;
+            ik[d] = (p.kr[d] != 0.0f) ? (double)__builtin_amdgcn_rcpf(p.kr[d]) : 0.0;
     }
 }
 
@@ -327,7 +352,7 @@ __device__ __forceinline__ double peel_tau(const JobView &J, CellBox c, const do
         const R xloc = xl * cr.s - (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz);
         const R kt = cr.k0 * voigt_H<R>(cr.a, xloc) + cr.kd;
         tau += (double)kt * l;
-        ++lc.v[C_PEEL_CROSSINGS];
+        lc.add(C_PEEL_CROSSINGS);
         if (tau > J.tau_peel_max) return -1.0;
         if (by_sphere) return tau;
 #pragma unroll
@@ -365,11 +390,11 @@ __device__ __forceinline__ void peel_off(const JobView &J, const Photon<R> &p,
         const R xc = ps.base + (dr[0] * ps.ua[0] + dr[1] * ps.ua[1] + dr[2] * ps.ua[2]) +
                      ps.grec * (muc - R(1));
         const R xl = F::div(xc + (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz), cr.s);
-        ++lc.v[C_PEELS];
+        lc.add(C_PEELS);
         const double tau = peel_tau<R>(J, p.c, p.r, d, id, xl, dr, lc);
         if (tau < 0.0) continue;
         const double w = (double)W * ::exp(-tau);
-        if (J.record) J.rec_peel[p.id * J.n_cams + i] += w;
+        if (J.record) J.rec_peel[p.id() * J.n_cams + i] += w;
         const int b = bin_of((double)xl, J.cam_xmin, J.cam_xmax, J.cam_nbins);
         if (b >= 1 && b <= J.cam_nbins)
             atomicAdd(J.cam_spec + (size_t)i * J.cam_nbins + (b - 1), w);
@@ -394,13 +419,12 @@ __device__ __forceinline__ void peel_off(const JobView &J, const Photon<R> &p,
 
 // Emission (Sec. 3.1.1): source position, isotropic direction, frequency,
 // first optical depth; draw order [source][blob offset] mu phi [x_nat, atom
-// velocity] tau.
+// velocity] tau.  cr receives the line data of the birth cell.
 template <typename R, bool CAMS>
 __device__ __forceinline__ void emit(const JobView &J, Photon<R> &p, uint64_t id,
-                                     LaneCounters &lc)
+                                     CellRec<R> &cr, LaneCounters &lc)
 {
     using F = Fn<R>;
-    p.id = id;
     p.events = 0;
     p.nscat = 0;
     p.status = 0;
@@ -424,13 +448,15 @@ __device__ __forceinline__ void emit(const JobView &J, Photon<R> &p, uint64_t id
         p.r[2] += J.sigma * (double)(q2 * c4);
     }
     isotropic_dir(p);
-    ++lc.v[C_EMITTED];
+    lc.add(C_EMITTED);
     p.x = R(0);
-    if (!locate(J.g, p.r, p.k, p.c)) {        // born outside the domain
+    double k[3], ik[3];
+    geom_dir(p, k, ik);
+    if (!locate(J.g, p.r, k, p.c)) {           // born outside the domain
         p.status = 1;
         return;
     }
-    const CellRec<R> cr = load_cell<R>(J.g, p.c.cell);
+    cr = load_cell<R>(J.g, p.c.cell);
     R x = R(0);
     R ua[3] = {R(0), R(0), R(0)};
     R xnat = R(0);
@@ -463,38 +489,41 @@ __device__ __forceinline__ void emit(const JobView &J, Photon<R> &p, uint64_t id
     p.tau = -(double)F::log(p.rng.next());
 }
 
-// Ray tracing (Sec. 3.1.2): march cell by cell until the optical depth is
-// spent (returns true with the photon at the interaction point, the cell's
-// line data in cr, the comoving frequency in xloc and the total opacity in
-// ktot) or the photon leaves the domain / reaches the event cap (false).
+// One step of the ray tracing (Sec. 3.1.2) in the photon's current cell,
+// whose line data the caller holds in cr.  Returns kCrossed after moving the
+// photon into the next cell (cr then holds that cell's data), kEvent with the
+// photon at its interaction point (comoving frequency in xloc, total opacity
+// in ktot), or kGone once it has left the domain or reached the event cap.
+enum { kCrossed = 0, kEvent = 1, kGone = 2 };
+
 template <typename R>
-__device__ __forceinline__ bool march(const JobView &J, Photon<R> &p, CellRec<R> &cr, R &xloc,
-                                      double &ktot, LaneCounters &lc)
+__device__ __forceinline__ int march_step(const JobView &J, Photon<R> &p, CellRec<R> &cr,
+                                          R &xloc, double &ktot, LaneCounters &lc)
 {
-    for (;;) {
+    int axis;
+    bool by_sphere;
+    double k[3], ik[3];
+    geom_dir(p, k, ik);
+    const double l_exit = exit_distance(J.g, p.c, p.r, k, ik, axis, by_sphere);
+    xloc = p.x * cr.s - (p.kr[0] * cr.ux + p.kr[1] * cr.uy + p.kr[2] * cr.uz);
+    const R kHI = cr.k0 * voigt_H<R>(cr.a, xloc);
+    ktot = (double)(kHI + cr.kd);
+    const double tau_cell = ktot * l_exit;
+    if (p.tau > tau_cell) {
+        p.tau -= tau_cell;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) p.r[d] += l_exit * k[d];
+        lc.add(C_CROSSINGS);
+        if (++p.events >= J.max_events) { p.status = 3; return kGone; }
+        if (by_sphere || !cross(J.g, p.c, p.r, k, axis)) { p.status = 1; return kGone; }
         cr = load_cell<R>(J.g, p.c.cell);
-        xloc = p.x * cr.s - (p.kr[0] * cr.ux + p.kr[1] * cr.uy + p.kr[2] * cr.uz);
-        int axis;
-        bool by_sphere;
-        const double l_exit = exit_distance(J.g, p.c, p.r, p.k, p.ik, axis, by_sphere);
-        const R kHI = cr.k0 * voigt_H<R>(cr.a, xloc);
-        ktot = (double)(kHI + cr.kd);
-        const double tau_cell = ktot * l_exit;
-        if (p.tau > tau_cell) {
-            p.tau -= tau_cell;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) p.r[d] += l_exit * p.k[d];
-            ++lc.v[C_CROSSINGS];
-            if (++p.events >= J.max_events) { p.status = 3; return false; }
-            if (by_sphere || !cross(J.g, p.c, p.r, p.k, axis)) { p.status = 1; return false; }
-            continue;
-        }
-        const double l = p.tau / ktot;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) p.r[d] += l * p.k[d];
-        if (++p.events >= J.max_events || !(p.r[0] == p.r[0])) { p.status = 3; return false; }
-        return true;
+        return kCrossed;
     }
+    const double l = p.tau / ktot;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p.r[d] += l * k[d];
+    if (++p.events >= J.max_events || !(p.r[0] == p.r[0])) { p.status = 3; return kGone; }
+    return kEvent;
 }
 
 // Interaction channel: grey dust with probability k_dust / k_tot (absorbed
@@ -509,7 +538,7 @@ __device__ __forceinline__ bool interact(const JobView &J, Photon<R> &p, const C
         if (p.rng.next() >= (R)J.g.albedo) { p.status = 2; return false; }
         isotropic_dir(p);
         p.x = F::div(xloc + (p.kr[0] * cr.ux + p.kr[1] * cr.uy + p.kr[2] * cr.uz), cr.s);
-        ++lc.v[C_SCAT_DUST];
+        lc.add(C_SCAT_DUST);
         if constexpr (CAMS) {
             if (J.n_cams > 0) {
                 const PeelSource<R> ps = {xloc, R(0), R(0), {R(0), R(0), R(0)}};
@@ -566,7 +595,7 @@ __device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
     const R xf = xloc - upar + (kf[0] * ua[0] + kf[1] * ua[1] + kf[2] * ua[2]) +
                  grec * (mu - R(1));              // eq. x_f
     ++p.nscat;
-    ++lc.v[C_SCAT_HI];
+    lc.add(C_SCAT_HI);
     if constexpr (CAMS) {
         if (J.n_cams > 0) {
             const PeelSource<R> ps = {xloc - upar, grec, rW, {ua[0], ua[1], ua[2]}};
@@ -582,33 +611,36 @@ template <typename R>
 __device__ __forceinline__ void finish(const JobView &J, const Photon<R> &p, LaneCounters &lc)
 {
     if (p.status == 1) {
-        ++lc.v[C_ESCAPED];
+        lc.add(C_ESCAPED);
         if (J.n_bins > 0) {
             const int b = bin_of((double)p.x, J.x_min, J.x_max, J.n_bins);
             atomicAdd(J.spectrum + b, 1ull);
         }
     } else if (p.status == 2) {
-        ++lc.v[C_ABSORBED];
+        lc.add(C_ABSORBED);
     } else {
-        ++lc.v[C_CAPPED];
+        lc.add(C_CAPPED);
     }
     if (J.record) {
-        J.rec_x[p.id] = (double)p.x;
-        J.rec_nscat[p.id] = p.nscat;
-        J.rec_status[p.id] = p.status;
+        const uint64_t id = p.id();
+        J.rec_x[id] = (double)p.x;
+        J.rec_nscat[id] = p.nscat;
+        J.rec_status[id] = p.status;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) J.rec_pos[3 * p.id + d] = J.box_min_cm[d] + p.r[d] * J.dx_cm;
+        for (int d = 0; d < 3; ++d) J.rec_pos[3 * id + d] = J.box_min_cm[d] + p.r[d] * J.dx_cm;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Cooperative u_par sampling.  The lanes of a wave that need a parallel atom
 // velocity (two-part or core proposal) post their requests in LDS; in each
-// round every lane of the wave evaluates one candidate: lane L works for the
-// (L mod m)-th open request (m open requests), on its candidate number
-// base + L / m.  The smallest accepted candidate number of a request is its
-// sequential result, so the outcome equals the one-lane loop exactly while
-// all 64 lanes stay busy until the last request of the wave is served.
+// round every lane of the wave evaluates one unit of candidates: lane L works
+// for the (L mod m)-th open request (m open requests), on its unit number
+// base + L / m.  A unit is one candidate in FP64 and the two candidates that
+// share a generator block in FP32.  The smallest accepted candidate number of
+// a request is its sequential result, so the outcome equals the one-lane loop
+// exactly while all 64 lanes stay busy until the last request of the wave is
+// served.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct UparSlot {
@@ -629,8 +661,9 @@ constexpr uint32_t kMaxUparRounds = 1u << 22;   // bound on rounds; never reache
 
 // All 64 lanes of the wave must call this together.  On return, lanes with
 // `need` hold the unsigned |u_par| in u and the accepted candidate number in t
-// (ok = false only if the round bound was hit).
-template <typename R>
+// (ok = false only if the round bound was hit).  KEY_UNIFORM: every lane's
+// generator key (the job seed) is the same wave-uniform value.
+template <typename R, bool KEY_UNIFORM>
 __device__ __forceinline__ uint32_t coop_upar(bool need, const UparReq<R> &q, const RngKey &key,
                                               uint64_t B0, R &u, uint32_t &t, bool &ok,
                                               UparSlot<R> *slots, int32_t *table,
@@ -665,27 +698,37 @@ __device__ __forceinline__ uint32_t coop_upar(bool need, const UparReq<R> &q, co
         UparReq<R> qq;
         qq.X = s.X; qq.a = s.a; qq.u0 = s.u0; qq.p = s.p; qq.th0 = s.th0; qq.regime = s.regime;
         RngKey kk;
-        kk.key0 = s.key0; kk.key1 = s.key1; kk.id0 = s.id0; kk.id1 = s.id1;
+        kk.key0 = KEY_UNIFORM ? key.key0 : s.key0;
+        kk.key1 = KEY_UNIFORM ? key.key1 : s.key1;
+        kk.id0 = s.id0; kk.id1 = s.id1;
         const uint64_t b0 = ((uint64_t)s.b0hi << 32) | s.b0lo;
         R uc;
-        const bool acc = upar_candidate<R>(qq, kk, b0, s.base + ss, uc);
+        uint32_t half = 0;
+        bool acc;
+        if constexpr (sizeof(R) == 8)
+            acc = upar_candidate<R>(qq, kk, b0, s.base + ss, uc);
+        else
+            acc = upar_pair_fp32(qq, kk, b0, s.base + ss, uc, half);
         if (acc) atomicMin(&first[rr], (uint32_t)lane);
         wave_lds_sync();
         uint32_t f = 64u;
         if (need) f = first[rank];
         const int src = (need && f < 64u) ? (int)f : lane;
         R got;
+        uint32_t got_half = 0;
         if constexpr (sizeof(R) == 8) {
             const uint64_t bits = __double_as_longlong(uc);
             const uint32_t lo = __shfl((uint32_t)bits, src), hi = __shfl((uint32_t)(bits >> 32), src);
             got = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
         } else {
             got = __shfl(uc, src);
+            got_half = __shfl(half, src);
         }
         if (need) {
             if (f < 64u) {
                 u = got;
-                t = base + f / (uint32_t)m;
+                const uint32_t unit = base + f / (uint32_t)m;
+                t = (sizeof(R) == 8) ? unit : 2u * unit + got_half;
                 need = false;
             } else {
                 base += (uint32_t)((64 - rank + m - 1) / m);
@@ -710,15 +753,19 @@ __device__ __forceinline__ int find_job(const LaunchView &L, uint64_t g)
 }
 
 // Persistent photon pool.  Each pass of the wave loop: idle lanes take new
-// photons from the shared queue (one atomic per wave), every live photon
-// marches to its next interaction, the wave serves all parallel-velocity
-// draws cooperatively, and the scatterings are completed.  SINGLE launches
-// carry one job, whose parameters then live in scalar registers.
+// photons from the shared queue (one atomic per wave); the photons in flight
+// take ray-tracing steps, the wave stepping on while at least L.march_min of
+// its lanes are still in flight (the rest resume in the next pass, so one
+// long flight does not hold the whole wave); the wave then serves all
+// parallel-velocity draws cooperatively and completes the scatterings.  A
+// photon's history does not depend on where the passes cut its flights.
+// SINGLE launches carry one job, whose parameters then live in scalar
+// registers.
 // Resident workgroups of 256 lanes per CU the register allocation aims for.
 template <typename R, bool CAMS>
 constexpr int transport_min_blocks()
 {
-    return (sizeof(R) == 4 && !CAMS) ? COLT_FP32_MIN_BLOCKS : 1;
+    return CAMS ? 1 : ((sizeof(R) == 4) ? COLT_FP32_MIN_BLOCKS : COLT_FP64_MIN_BLOCKS);
 }
 
 template <typename R, bool CAMS, bool SINGLE>
@@ -727,18 +774,22 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
     __shared__ UparSlot<R> s_slots[4][64];
     __shared__ int32_t s_table[4][64];
     __shared__ uint32_t s_first[4][64];
+    __shared__ unsigned long long s_counts[kLaneCounters][kMaxBlock];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + wave) & (kCounterSlots - 1));
     Photon<R> p;
     p.status = 0;
+    CellRec<R> cr;                 // line data of the photon's cell while it lives
     LaneCounters lc;
+    lc.col = &s_counts[0][threadIdx.x];
 #pragma unroll
-    for (int i = 0; i < kLaneCounters; ++i) lc.v[i] = 0;
+    for (int i = 0; i < kLaneCounters; ++i) s_counts[i][threadIdx.x] = 0ull;
     const JobView *J = SINGLE ? L.jobs : nullptr;
     const uint64_t total = L.prefix[L.n_jobs];
-    bool have = false, drained = total == 0;
+    const int march_min = L.march_min;
+    bool have = false, moving = false, drained = total == 0;
     for (;;) {
         if (!drained) {
             const uint64_t need = __ballot(!have);
@@ -766,9 +817,14 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
                             }
                             id = L.first_id[j] + (g - L.prefix[j]);
                         }
-                        emit<R, CAMS>(*J, p, id, lc);
+                        emit<R, CAMS>(*J, p, id, cr, lc);
                         have = true;
-                        if (p.status != 0) { finish<R>(*J, p, lc); have = false; }
+                        moving = true;
+                        if (p.status != 0) {
+                            finish<R>(*J, p, lc);
+                            have = false;
+                            moving = false;
+                        }
                     }
                 }
             }
@@ -777,48 +833,66 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
             if (drained) break;
             continue;          // lanes were refilled with photons born outside
         }
-        bool hi = false;
-        CellRec<R> cr;
+        if constexpr (SINGLE) {
+            // one job: its seed, the generator key, is wave-uniform
+            p.rng.key.key0 = (uint32_t)J->seed;
+            p.rng.key.key1 = (uint32_t)(J->seed >> 32);
+        }
+        bool event = false;
         R xloc = R(0);
+        double ktot = 0.0;
+        for (;;) {
+            if (moving) {
+                const int st = march_step<R>(*J, p, cr, xloc, ktot, lc);
+                if (st != kCrossed) {
+                    moving = false;
+                    event = st == kEvent;
+                }
+            }
+            const int in_flight = __popcll(__ballot(moving));
+            if (in_flight == 0 || in_flight < march_min) break;
+        }
+        bool hi = false;
         UparReq<R> q;
         q.regime = UPAR_GAUSS;
         uint64_t B0 = 0;
-        if (have) {
-            double ktot;
-            if (march<R>(*J, p, cr, xloc, ktot, lc) && interact<R, CAMS>(*J, p, cr, xloc, ktot, lc)) {
+        if (event) {
+            if (interact<R, CAMS>(*J, p, cr, xloc, ktot, lc)) {
                 hi = true;
                 q = upar_setup<R>(cr.a, xloc, cr.xcw);
                 B0 = p.rng.align();
+            } else if (p.status == 0) {
+                moving = true;                    // dust scattering: a new flight
             }
         }
         R u = R(0);
         uint32_t tacc = 0;
         bool ok = true;
-        const uint32_t rounds = coop_upar<R>(hi && q.regime != UPAR_GAUSS, q, p.rng.key, B0, u,
+        const uint32_t rounds = coop_upar<R, SINGLE>(hi && q.regime != UPAR_GAUSS, q, p.rng.key, B0, u,
                                              tacc, ok, s_slots[wave], s_table[wave],
                                              s_first[wave]);
         if (lane == 0 && J) {
-            lc.v[C_ROUNDS] += rounds;
-            ++lc.v[C_PASSES];
+            lc.add(C_ROUNDS, rounds);
+            lc.add(C_PASSES);
         }
         if (hi) {
             if (q.regime == UPAR_GAUSS) {
                 u = upar_gauss<R>(q, p.rng.key, B0);
                 p.rng.k += Rng<R>::kPerBlock;
             } else {
-                lc.v[C_UPAR_TRIES] += tacc + 1;
-                p.rng.k += (uint64_t)upar_stride<R>(q.regime) * (tacc + 1);
+                lc.add(C_UPAR_TRIES, tacc + 1);
+                p.rng.k += upar_advance<R>(q.regime, tacc);
                 if (!ok) p.status = 3;
             }
-            if (p.status == 0)
+            if (p.status == 0) {
                 scatter_finish<R, CAMS>(*J, p, cr, xloc, (xloc < R(0)) ? -u : u, lc);
+                moving = true;
+            }
         }
         if (have && p.status != 0) {
             finish<R>(*J, p, lc);
             have = false;
-            if (lc.v[C_SCAT_HI] > (1u << 30) || lc.v[C_UPAR_TRIES] > (1u << 30) ||
-                lc.v[C_PEEL_CROSSINGS] > (1u << 30) || lc.v[C_CROSSINGS] > (1u << 30))
-                flush_counters(J, lc, slot);
+            moving = false;
         }
     }
     if (SINGLE || J) flush_counters(J, lc, slot);
@@ -921,7 +995,8 @@ __global__ void k_voigt(int64_t n, const double *a, const double *x, double *out
 }
 
 // what 0: u_par with the cooperative sampler (x = p1); what 4: the same with
-// x varying across lanes, x_i = p1 + 0.41 (i mod 23) (-1)^i.
+// x varying across lanes, x_i = p1 + 0.41 (i mod 23) (-1)^i; what 5 and 6:
+// the same two with the one-lane sequential sampler.
 template <typename R>
 __global__ __launch_bounds__(256) void k_sample(int what, double p0, double p1, double p2,
                                                 uint64_t seed, int64_t n, double *out,
@@ -943,14 +1018,14 @@ __global__ __launch_bounds__(256) void k_sample(int what, double p0, double p1, 
         R u = R(0);
         uint32_t t = 0;
         bool ok = true;
-        coop_upar<R>(live && q.regime != UPAR_GAUSS, q, rng.key, B0, u, t, ok, s_slots[wave],
+        coop_upar<R, false>(live && q.regime != UPAR_GAUSS, q, rng.key, B0, u, t, ok, s_slots[wave],
                      s_table[wave], s_first[wave]);
         if (!live) return;
         if (q.regime == UPAR_GAUSS) {
             u = upar_gauss<R>(q, rng.key, B0);
             rng.k += Rng<R>::kPerBlock;
         } else {
-            rng.k += (uint64_t)upar_stride<R>(q.regime) * (t + 1);
+            rng.k += upar_advance<R>(q.regime, t);
         }
         out[i] = (double)((x < R(0)) ? -u : u);
         draws[i] = ok ? (int32_t)rng.k : -1;
@@ -964,9 +1039,11 @@ __global__ __launch_bounds__(256) void k_sample(int what, double p0, double p1, 
         out[2 * i + 1] = (double)u2;
     } else if (what == 2) {
         out[i] = (double)draw_mu<R>((R)p0, rng);
-    } else if (what == 5) {
+    } else if (what == 5 || what == 6) {
+        R x = (R)p1;
+        if (what == 6) x = (R)(p1 + 0.41 * (double)(i % 23) * ((i & 1) ? -1.0 : 1.0));
         uint32_t tries = 0;
-        out[i] = (double)draw_upar<R>((R)p0, (R)p1, (R)p2, rng, tries);
+        out[i] = (double)draw_upar<R>((R)p0, x, (R)p2, rng, tries);
         draws[i] = (int32_t)rng.k;
     } else {
         const int64_t m = (int64_t)p0;

@@ -28,15 +28,17 @@ def test_neufeld_slab_tau0_1e8(precision):
     J = stats.slab_J(grid, atau0)
     ref_mean = np.trapezoid(np.abs(grid) * J, grid) / np.trapezoid(J, grid)
     assert abs(np.abs(x).mean() / ref_mean - 1) < 0.03
-    # binned spectrum against the analytic J near the peaks (within ~5 %)
-    edges = np.linspace(-120, 120, 241)
+    # spectrum in 4-Doppler-width bins against the analytic J near the peaks:
+    # Poisson noise is ~1 % of the peak per bin there, and the paper reports
+    # the analytic form to hold to ~5 % at this depth
+    edges = np.linspace(-120, 120, 61)
     h, _ = np.histogram(x, edges)
     centre = 0.5 * (edges[1:] + edges[:-1])
     Jb = stats.slab_J(centre, atau0)
     model = Jb / Jb.sum() * n
     peak = model > 0.5 * model.max()
     dev = np.abs(h[peak] - model[peak]) / model.max()
-    assert dev.max() < 0.08
+    assert dev.max() < 0.07
     assert abs((x > 0).mean() - 0.5) < 4 * math.sqrt(0.25 / n)
 
 
