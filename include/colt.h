@@ -156,9 +156,10 @@ typedef struct {
                                           /* events (see colt_last_kernel_ms)      */
     int32_t march_min;                    /* a wave keeps ray tracing while at     */
                                           /* least this many of its 64 lanes are   */
-                                          /* in flight; 0 = default (16 FP32-bulk, */
-                                          /* 8 FP64), 1 = each                     */
-                                          /* flight ends within its pass           */
+                                          /* in flight (with fewer than 64 live    */
+                                          /* photons, a quarter of them); 0 =      */
+                                          /* default (16), 1 = every flight ends   */
+                                          /* within its pass                       */
 } colt_launch;
 
 typedef struct {

@@ -145,6 +145,7 @@ struct Fn<double> {
     static __device__ __forceinline__ double log(double x) { return ::log(x); }
     static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
     static __device__ __forceinline__ double cbrt(double x) { return ::cbrt(x); }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
     static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
     static __device__ __forceinline__ double tan(double x) { return ::tan(x); }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
@@ -168,7 +169,12 @@ struct Fn<float> {
         return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
     }
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_sqrtf(x); }
-    static __device__ __forceinline__ float cbrt(float x) { return ::cbrtf(x); }
+    // x >= 0: 2^(log2(x) / 3) on the transcendental unit (a few ulp)
+    static __device__ __forceinline__ float cbrt(float x)
+    {
+        return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f));
+    }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
     static __device__ __forceinline__ float div(float a, float b)
     {
@@ -447,7 +453,16 @@ __device__ __forceinline__ void perp_basis(const R k[3], R e1[3], R e2[3])
 {
     using F = Fn<R>;
     const R kz = (k[2] < R(0)) ? -k[2] : k[2];
-    if (kz <= R(0.9)) {
+    if constexpr (sizeof(R) == 4) {
+        // without branches: e1 = (a, -b, 0) or (0, a, -b), scaled by 1/|(a, b)|
+        const bool zax = kz <= R(0.9);
+        const R a = zax ? k[1] : k[2], b = zax ? k[0] : k[1];
+        const R inv = F::rsqrt(a * a + b * b);
+        const R ea = a * inv, eb = -b * inv;
+        e1[0] = zax ? ea : R(0);
+        e1[1] = zax ? eb : ea;
+        e1[2] = zax ? R(0) : eb;
+    } else if (kz <= R(0.9)) {
         const R n = F::sqrt(k[0] * k[0] + k[1] * k[1]);
         e1[0] = F::div(k[1], n); e1[1] = F::div(-k[0], n); e1[2] = R(0);
     } else {

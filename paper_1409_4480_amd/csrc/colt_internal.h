@@ -13,9 +13,9 @@ constexpr int kCounterSlots = 64;          // counter copies per job (spread ato
 constexpr int kNumCounters = 16;
 constexpr int kMaxCams = 64;
 // Lanes in flight that keep a wave ray tracing (measured best on the 64^3
-// dusty sphere: 16 of 64 in FP32-bulk, 8 in FP64).
+// dusty sphere: 16 of 64 lanes).
 constexpr int kDefaultMarchMinFp32 = 16;
-constexpr int kDefaultMarchMinFp64 = 8;
+constexpr int kDefaultMarchMinFp64 = 16;
 
 // Line data of one cell for the march: opacity at line centre per grid unit,
 // damping parameter, v_ref / v_th, dust opacity per grid unit, bulk velocity

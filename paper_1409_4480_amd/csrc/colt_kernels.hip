@@ -15,7 +15,7 @@
 #include "colt_launch.h"
 
 #ifndef COLT_FP32_MIN_BLOCKS
-#define COLT_FP32_MIN_BLOCKS 3
+#define COLT_FP32_MIN_BLOCKS 4
 #endif
 #ifndef COLT_FP64_MIN_BLOCKS
 #define COLT_FP64_MIN_BLOCKS 2
@@ -587,9 +587,16 @@ __device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
     R kf[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) kf[d] = mu * p.kr[d] + st * (cph * e1[d] + sph * e2[d]);
-    const R nk = F::sqrt(kf[0] * kf[0] + kf[1] * kf[1] + kf[2] * kf[2]);
+    const R nk2 = kf[0] * kf[0] + kf[1] * kf[1] + kf[2] * kf[2];
+    if constexpr (sizeof(R) == 4) {
+        const R inv = F::rsqrt(nk2);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) kf[d] = F::div(kf[d], nk);
+        for (int d = 0; d < 3; ++d) kf[d] *= inv;
+    } else {
+        const R nk = F::sqrt(nk2);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) kf[d] = F::div(kf[d], nk);
+    }
     R grec = R(0);
     if (J.recoil) grec = load_aux<R>(J.g, p.c.cell).g;
     const R xf = xloc - upar + (kf[0] * ua[0] + kf[1] * ua[1] + kf[2] * ua[2]) +
@@ -829,10 +836,8 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
                 }
             }
         }
-        if (!__any(have)) {
-            if (drained) break;
-            continue;          // lanes were refilled with photons born outside
-        }
+        const bool any_have = __any(have);
+        if (any_have) {
         if constexpr (SINGLE) {
             // one job: its seed, the generator key, is wave-uniform
             p.rng.key.key0 = (uint32_t)J->seed;
@@ -841,6 +846,11 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
         bool event = false;
         R xloc = R(0);
         double ktot = 0.0;
+        // with few photons left in the wave a pass need not wait for many
+        // flights: the threshold shrinks with the number of live lanes
+        const int live = __popcll(__ballot(have));
+        const int quarter = (live + 3) >> 2;
+        const int stop_below = (march_min < quarter) ? march_min : quarter;
         for (;;) {
             if (moving) {
                 const int st = march_step<R>(*J, p, cr, xloc, ktot, lc);
@@ -850,7 +860,7 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
                 }
             }
             const int in_flight = __popcll(__ballot(moving));
-            if (in_flight == 0 || in_flight < march_min) break;
+            if (in_flight == 0 || in_flight < stop_below) break;
         }
         bool hi = false;
         UparReq<R> q;
@@ -894,6 +904,8 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
             have = false;
             moving = false;
         }
+        }
+        if (!any_have && drained) break;
     }
     if (SINGLE || J) flush_counters(J, lc, slot);
 }
