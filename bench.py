@@ -34,6 +34,28 @@ OPS_FP32 = {"uniform": 33, "scat_hi": 400, "upar_tries": 24, "crossings": 65,
 # emission; one channel draw per interaction in dusty cells
 DRAWS_PER = {"upar_tries": 3, "scat_hi": 5, "scat_dust": 4, "emitted": 3}
 
+# HBM bytes per launch of the FP32-bulk transport kernel on this workload,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration
+# (profiles/k_transport_fp32_dusty_sphere_64.md).  They hold for the kernel
+# sources they were taken on; for any other sources traffic is reported null.
+TRAFFIC = {"sources_sha256": None, "fetch_bytes": None, "write_bytes": None}
+KERNEL_SOURCES = ["colt_kernels.hip", "colt_device.h", "colt_internal.h"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1409_4480_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    if TRAFFIC["sources_sha256"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
+        return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+    return None
+
 
 def algorithmic_ops(c, dusty=True):
     draws = sum(DRAWS_PER[k] * c[k] for k in DRAWS_PER)
@@ -123,6 +145,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=4,
+                    help="jobs of the workload fused in one launch for the batched figure "
+                         "(0 or 1 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=48,
                     help="jobs in the serving stream (0 skips the serving section)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -208,10 +233,29 @@ def main():
                      max(64 * sum(c["upar_rounds"] for c in cnt), 1)},
         "grid_setup_ms": grid_setup_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
                      "kernel": "k_transport<float>", "kernel_ms": kern_avg_ms,
                      "ops_per_launch": ops},
     }
+    # the same steps fused: args.steps jobs of the workload in one persistent
+    # launch (per-job queues), so that one job's long-lived last photons share
+    # the device with the others' bulk
+    if args.batch > 1:
+        jobs = [colt.Job(grid, wl["source"], dict(wl["params"], seed=1409448002 + i),
+                         precision=colt.FP32_BULK) for i in range(args.batch)]
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        colt.transport(jobs, block=args.block, blocks_per_cu=args.blocks_per_cu,
+                       time_kernel=True)
+        outs = [j.tally(wait=True) for j in jobs]
+        elb = time.perf_counter() - tb
+        scat_b = sum(o["counters"]["scat_hi"] for o in outs)
+        for j in jobs:
+            j.release()
+        result["batched_steps"] = {"jobs": args.batch, "value": scat_b / elb,
+                                   "unit": "scatterings/s", "ms": elb * 1e3,
+                                   "kernel_ms": colt.last_kernel_ms(),
+                                   "note": "the jobs of as many steps in one launch"}
     if not args.no_fp64:
         el64, lat64, kern64, cnt64 = run_steps(colt.FP64, args.steps, 1409448002)
         scat64 = sum(c["scat_hi"] for c in cnt64)

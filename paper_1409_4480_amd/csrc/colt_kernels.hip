@@ -279,6 +279,22 @@ __device__ __forceinline__ void flush_counters(const JobView *J, LaneCounters &l
     }
 }
 
+// End of a single-job launch: the wave sums its lanes' columns first, so the
+// job's counters take one atomic per counter per wave.  All 64 lanes call it.
+__device__ __forceinline__ void flush_counters_wave(const JobView *J, LaneCounters &lc, int slot)
+{
+    unsigned long long *dst = J->counters + (size_t)slot * kNumCounters;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < kLaneCounters; ++i) {
+        unsigned long long v = lc.col[i * kMaxBlock];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0 && v) atomicAdd(dst + i, v);
+        lc.col[i * kMaxBlock] = 0ull;
+    }
+}
+
 template <typename R>
 struct Photon {
     double r[3];
@@ -907,7 +923,10 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
         }
         if (!any_have && drained) break;
     }
-    if (SINGLE || J) flush_counters(J, lc, slot);
+    if constexpr (SINGLE)
+        flush_counters_wave(J, lc, slot);
+    else if (J)
+        flush_counters(J, lc, slot);
 }
 
 // ---------------------------------------------------------------------------
