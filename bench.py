@@ -135,6 +135,38 @@ def serve_section(n_jobs):
             "speedup_batched_vs_serial_fp64": batched["scatterings_per_s"] / (scat / serial)}
 
 
+def camera_section(n_photons=262144, cap=2000):
+    """Peel-off throughput on the camera workloads: the 128^3 first-galaxy halo
+    (8 cameras, 256^2 images, 1000 bins) and the ~2e6-leaf NFW octree (4
+    cameras, 512^2 images), a full photon pool each, every photon followed for
+    its first `cap` events -- the steady state of those jobs, whose full
+    histories run to ~1e6 scatterings per photon."""
+    import torch
+
+    from paper_1409_4480_amd import colt, inputs
+
+    out = {}
+    for name, wl in (("halo_128cube_8cams", inputs.halo(n_photons=n_photons)),
+                     ("nfw_octree_2e6_leaves_4cams", inputs.nfw_octree(n_photons=n_photons))):
+        wl["params"]["max_events"] = cap
+        grid = colt.Grid(wl["grid"])
+        for rep in range(2):
+            job = colt.Job(grid, wl["source"], wl["params"], precision=colt.FP32_BULK,
+                           max_events=cap)
+            torch.cuda.synchronize()
+            colt.transport([job], time_kernel=True)
+            c = job.tally(wait=True)["counters"]
+            ms = colt.last_kernel_ms()
+            job.release()
+        grid.release()
+        out[name] = {"scatterings_per_s": c["scat_hi"] / (ms * 1e-3), "kernel_ms": ms,
+                     "photons": n_photons, "events_cap": cap,
+                     "peels_per_scattering": c["peels"] / max(c["scat_hi"], 1),
+                     "peel_crossings_per_s": c["peel_crossings"] / (ms * 1e-3),
+                     "precision": "FP32-bulk"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +180,8 @@ def main():
     ap.add_argument("--batch", type=int, default=4,
                     help="jobs of the workload fused in one launch for the batched figure "
                          "(0 or 1 skips it)")
+    ap.add_argument("--no-cams", action="store_true",
+                    help="skip the camera (peel-off) workloads")
     ap.add_argument("--serve-jobs", type=int, default=48,
                     help="jobs in the serving stream (0 skips the serving section)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -268,6 +302,8 @@ def main():
             sum(c["emitted"] for c in cnt64)}
         result["speedup_mixed_vs_fp64"] = value / (scat64 / el64)
     grid.release()
+    if not args.no_cams:
+        result["cameras"] = camera_section()
     if args.serve_jobs > 0:
         result["serving"] = serve_section(args.serve_jobs)
         result["latency_ms"] = {"p50": result["serving"]["poisson"]["p50_ms"],

@@ -351,20 +351,22 @@ __device__ __forceinline__ void isotropic_dir(Photon<R> &p)
     set_dir(p, st * c, st * s, mu);
 }
 
-// Optical depth along camera direction d (inverse id) from r in cell c to the
-// domain edge for lab frequency xl; negative once above the cut-off.
+// Optical depth along camera direction d (inverse id) from r in cell c (whose
+// line data the caller holds in cr0) to the domain edge for lab frequency xl,
+// added to tau0; negative once above the cut-off.
 template <typename R>
-__device__ __forceinline__ double peel_tau(const JobView &J, CellBox c, const double r0[3],
-                                           const double d[3], const double id[3], R xl,
-                                           const R dr[3], LaneCounters &lc)
+__device__ __forceinline__ double peel_tau(const JobView &J, CellBox c, const CellRec<R> &cr0,
+                                           const double r0[3], const double d[3],
+                                           const double id[3], R xl, const R dr[3],
+                                           double tau0, LaneCounters &lc)
 {
     double r[3] = {r0[0], r0[1], r0[2]};
-    double tau = 0.0;
+    double tau = tau0;
+    CellRec<R> cr = cr0;
     for (;;) {
         int axis;
         bool by_sphere;
         const double l = exit_distance(J.g, c, r, d, id, axis, by_sphere);
-        const CellRec<R> cr = load_cell<R>(J.g, c.cell);
         const R xloc = xl * cr.s - (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz);
         const R kt = cr.k0 * voigt_H<R>(cr.a, xloc) + cr.kd;
         tau += (double)kt * l;
@@ -374,6 +376,7 @@ __device__ __forceinline__ double peel_tau(const JobView &J, CellBox c, const do
 #pragma unroll
         for (int e = 0; e < 3; ++e) r[e] += l * d[e];
         if (!cross(J.g, c, r, d, axis)) return tau;
+        cr = load_cell<R>(J.g, c.cell);
     }
 }
 
@@ -387,12 +390,82 @@ struct PeelSource {
     R ua[3];
 };
 
+// Deferred peel-off marches.  A camera's march from an event usually ends in
+// the event's own cell (optical depth above the cut-off), which the event's
+// lane settles at once; a march that goes on is posted to its wave's queue in
+// LDS and continued by whichever lanes are free, a step at a time, in later
+// passes -- so one long march to the domain edge does not hold the wave.  The
+// optical depth and the tallies are the same either way.
+constexpr int kPeelSlots = 64;
+
+template <typename R>
+struct PeelTask {
+    double r[3];              // position on the entry face of the current cell
+    double lo[3];             // current cell box
+    double size;
+    double tau;               // optical depth so far
+    R xl, W;                  // lab frequency and phase weight of the contribution
+    int32_t cell, cam, bin, pix, job;
+    uint32_t id0, id1;        // photon id (per-photon records)
+};
+
+template <typename R>
+struct PeelQueue {
+    PeelTask<R> *slots;       // the wave's kPeelSlots tasks
+    int *count;               // tasks posted; beyond kPeelSlots the lane ran them itself
+    int job;                  // the lane's job index in the launch
+};
+
+// W exp(-tau) of camera `cam` into its spectrum bin and image pixel (and the
+// photon's record).
+__device__ __forceinline__ void peel_tally(const JobView &J, int cam, int bin, int pix,
+                                           uint64_t id, double w)
+{
+    if (J.record) atomicAdd(J.rec_peel + id * J.n_cams + cam, w);
+    if (bin >= 1 && bin <= J.cam_nbins)
+        atomicAdd(J.cam_spec + (size_t)cam * J.cam_nbins + (bin - 1), w);
+    if (pix >= 0) atomicAdd(J.cam_img + (size_t)cam * J.npix * J.npix + pix, w);
+}
+
+// One step of a deferred march: the optical depth of the task's current cell.
+// Returns 0 when it goes on in the next cell, 1 at the domain edge (tally), 2
+// above the cut-off (no contribution).
+template <typename R>
+__device__ __forceinline__ int peel_step(const JobView &J, PeelTask<R> &t, LaneCounters &lc)
+{
+    const double *cam = J.cam + 12 * t.cam;
+    const double d[3] = {cam[0], cam[1], cam[2]};
+    const double id[3] = {cam[3], cam[4], cam[5]};
+    const R dr[3] = {(R)cam[0], (R)cam[1], (R)cam[2]};
+    CellBox c;
+    c.lo[0] = t.lo[0]; c.lo[1] = t.lo[1]; c.lo[2] = t.lo[2];
+    c.size = t.size;
+    c.cell = t.cell;
+    const CellRec<R> cr = load_cell<R>(J.g, c.cell);
+    int axis;
+    bool by_sphere;
+    const double l = exit_distance(J.g, c, t.r, d, id, axis, by_sphere);
+    const R xloc = t.xl * cr.s - (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz);
+    const R kt = cr.k0 * voigt_H<R>(cr.a, xloc) + cr.kd;
+    t.tau += (double)kt * l;
+    lc.add(C_PEEL_CROSSINGS);
+    if (t.tau > J.tau_peel_max) return 2;
+    if (by_sphere) return 1;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) t.r[e] += l * d[e];
+    if (!cross(J.g, c, t.r, d, axis)) return 1;
+    t.lo[0] = c.lo[0]; t.lo[1] = c.lo[1]; t.lo[2] = c.lo[2];
+    t.size = c.size;
+    t.cell = c.cell;
+    return 0;
+}
+
 // One next-event contribution per camera from an event at p.r in cell p.c
 // (Sec. 6.1, eq. SB): W exp(-tau_esc) into the camera spectrum and image.
 template <typename R>
 __device__ __forceinline__ void peel_off(const JobView &J, const Photon<R> &p,
                                          const CellRec<R> &cr, const PeelSource<R> &ps,
-                                         LaneCounters &lc)
+                                         PeelQueue<R> &pq, LaneCounters &lc)
 {
     using F = Fn<R>;
     const R wn = R(1) + F::div(ps.rW, R(3));
@@ -407,29 +480,71 @@ __device__ __forceinline__ void peel_off(const JobView &J, const Photon<R> &p,
                      ps.grec * (muc - R(1));
         const R xl = F::div(xc + (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz), cr.s);
         lc.add(C_PEELS);
-        const double tau = peel_tau<R>(J, p.c, p.r, d, id, xl, dr, lc);
-        if (tau < 0.0) continue;
-        const double w = (double)W * ::exp(-tau);
-        if (J.record) J.rec_peel[p.id() * J.n_cams + i] += w;
-        const int b = bin_of((double)xl, J.cam_xmin, J.cam_xmax, J.cam_nbins);
-        if (b >= 1 && b <= J.cam_nbins)
-            atomicAdd(J.cam_spec + (size_t)i * J.cam_nbins + (b - 1), w);
-        if (J.npix <= 0) continue;
-        double pu = 0.0, pv = 0.0;
+        // the event's own cell, whose line data are at hand
+        CellBox c = p.c;
+        double r[3] = {p.r[0], p.r[1], p.r[2]};
+        int axis;
+        bool by_sphere;
+        const double l = exit_distance(J.g, c, r, d, id, axis, by_sphere);
+        const R xloc = xl * cr.s - (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz);
+        const R kt = cr.k0 * voigt_H<R>(cr.a, xloc) + cr.kd;
+        double tau = (double)kt * l;
+        lc.add(C_PEEL_CROSSINGS);
+        if (tau > J.tau_peel_max) continue;
+        // the contribution may count: its spectrum bin and image pixel
+        const int bin = bin_of((double)xl, J.cam_xmin, J.cam_xmax, J.cam_nbins);
+        int pix = -1;
+        if (J.npix > 0) {
+            double pu = 0.0, pv = 0.0;
 #pragma unroll
-        for (int e = 0; e < 3; ++e) {
-            const double rc = p.r[e] - J.g.centre[e];
-            pu += rc * cam[6 + e];
-            pv += rc * cam[9 + e];
+            for (int e = 0; e < 3; ++e) {
+                const double rc = p.r[e] - J.g.centre[e];
+                pu += rc * cam[6 + e];
+                pv += rc * cam[9 + e];
+            }
+            pu = pu / J.fov + 0.5;
+            pv = pv / J.fov + 0.5;
+            if (pu >= 0.0 && pu < 1.0 && pv >= 0.0 && pv < 1.0) {
+                int iu = (int)(pu * J.npix), iv = (int)(pv * J.npix);
+                iu = (iu >= J.npix) ? J.npix - 1 : iu;
+                iv = (iv >= J.npix) ? J.npix - 1 : iv;
+                pix = iv * J.npix + iu;
+            }
         }
-        pu = pu / J.fov + 0.5;
-        pv = pv / J.fov + 0.5;
-        if (pu >= 0.0 && pu < 1.0 && pv >= 0.0 && pv < 1.0) {
-            int iu = (int)(pu * J.npix), iv = (int)(pv * J.npix);
-            iu = (iu >= J.npix) ? J.npix - 1 : iu;
-            iv = (iv >= J.npix) ? J.npix - 1 : iv;
-            atomicAdd(J.cam_img + ((size_t)i * J.npix + iv) * J.npix + iu, w);
+        bool edge = by_sphere;
+        if (!edge) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) r[e] += l * d[e];
+            edge = !cross(J.g, c, r, d, axis);
         }
+        if (!edge) {
+            const int slot = atomicAdd(pq.count, 1);
+            if (slot < kPeelSlots) {
+                PeelTask<R> t;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    t.r[e] = r[e];
+                    t.lo[e] = c.lo[e];
+                }
+                t.size = c.size;
+                t.tau = tau;
+                t.xl = xl;
+                t.W = W;
+                t.cell = c.cell;
+                t.cam = i;
+                t.bin = bin;
+                t.pix = pix;
+                t.job = pq.job;
+                t.id0 = p.rng.key.id0;
+                t.id1 = p.rng.key.id1;
+                pq.slots[slot] = t;
+                continue;
+            }
+            // queue full: finish the march here
+            tau = peel_tau<R>(J, c, load_cell<R>(J.g, c.cell), r, d, id, xl, dr, tau, lc);
+            if (tau < 0.0) continue;
+        }
+        peel_tally(J, i, bin, pix, p.id(), (double)W * ::exp(-tau));
     }
 }
 
@@ -438,7 +553,7 @@ __device__ __forceinline__ void peel_off(const JobView &J, const Photon<R> &p,
 // velocity] tau.  cr receives the line data of the birth cell.
 template <typename R, bool CAMS>
 __device__ __forceinline__ void emit(const JobView &J, Photon<R> &p, uint64_t id,
-                                     CellRec<R> &cr, LaneCounters &lc)
+                                     CellRec<R> &cr, PeelQueue<R> &pq, LaneCounters &lc)
 {
     using F = Fn<R>;
     p.events = 0;
@@ -499,7 +614,7 @@ __device__ __forceinline__ void emit(const JobView &J, Photon<R> &p, uint64_t id
     if constexpr (CAMS) {
         if (J.n_cams > 0) {
             const PeelSource<R> ps = {xnat, R(0), R(0), {ua[0], ua[1], ua[2]}};
-            peel_off<R>(J, p, cr, ps, lc);
+            peel_off<R>(J, p, cr, ps, pq, lc);
         }
     }
     p.tau = -(double)F::log(p.rng.next());
@@ -547,7 +662,8 @@ __device__ __forceinline__ int march_step(const JobView &J, Photon<R> &p, CellRe
 // the comoving frequency kept); otherwise an H I scattering (returns true).
 template <typename R, bool CAMS>
 __device__ __forceinline__ bool interact(const JobView &J, Photon<R> &p, const CellRec<R> &cr,
-                                         R xloc, double ktot, LaneCounters &lc)
+                                         R xloc, double ktot, PeelQueue<R> &pq,
+                                         LaneCounters &lc)
 {
     using F = Fn<R>;
     if (cr.kd > R(0) && p.rng.next() < F::div(cr.kd, (R)ktot)) {
@@ -558,7 +674,7 @@ __device__ __forceinline__ bool interact(const JobView &J, Photon<R> &p, const C
         if constexpr (CAMS) {
             if (J.n_cams > 0) {
                 const PeelSource<R> ps = {xloc, R(0), R(0), {R(0), R(0), R(0)}};
-                peel_off<R>(J, p, cr, ps, lc);
+                peel_off<R>(J, p, cr, ps, pq, lc);
             }
         }
         p.tau = -(double)F::log(p.rng.next());
@@ -574,7 +690,7 @@ __device__ __forceinline__ bool interact(const JobView &J, Photon<R> &p, const C
 template <typename R, bool CAMS>
 __device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
                                                const CellRec<R> &cr, R xloc, R upar,
-                                               LaneCounters &lc)
+                                               PeelQueue<R> &pq, LaneCounters &lc)
 {
     using F = Fn<R>;
     const R a = cr.a, xcw = cr.xcw;
@@ -622,7 +738,7 @@ __device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
     if constexpr (CAMS) {
         if (J.n_cams > 0) {
             const PeelSource<R> ps = {xloc - upar, grec, rW, {ua[0], ua[1], ua[2]}};
-            peel_off<R>(J, p, cr, ps, lc);
+            peel_off<R>(J, p, cr, ps, pq, lc);
         }
     }
     set_dir(p, kf[0], kf[1], kf[2]);
@@ -798,10 +914,18 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
     __shared__ int32_t s_table[4][64];
     __shared__ uint32_t s_first[4][64];
     __shared__ unsigned long long s_counts[kLaneCounters][kMaxBlock];
+    __shared__ PeelTask<R> s_peel[CAMS ? 4 : 1][CAMS ? kPeelSlots : 1];
+    __shared__ int s_peel_n[4];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + wave) & (kCounterSlots - 1));
+    PeelQueue<R> pq;
+    pq.slots = s_peel[CAMS ? wave : 0];
+    pq.count = &s_peel_n[wave];
+    pq.job = 0;
+    if (lane == 0) s_peel_n[wave] = 0;
+    wave_lds_sync();
     Photon<R> p;
     p.status = 0;
     CellRec<R> cr;                 // line data of the photon's cell while it lives
@@ -840,7 +964,8 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
                             }
                             id = L.first_id[j] + (g - L.prefix[j]);
                         }
-                        emit<R, CAMS>(*J, p, id, cr, lc);
+                        if constexpr (!SINGLE) pq.job = (int)(J - L.jobs);
+                        emit<R, CAMS>(*J, p, id, cr, pq, lc);
                         have = true;
                         moving = true;
                         if (p.status != 0) {
@@ -854,72 +979,115 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
         }
         const bool any_have = __any(have);
         if (any_have) {
-        if constexpr (SINGLE) {
-            // one job: its seed, the generator key, is wave-uniform
-            p.rng.key.key0 = (uint32_t)J->seed;
-            p.rng.key.key1 = (uint32_t)(J->seed >> 32);
-        }
-        bool event = false;
-        R xloc = R(0);
-        double ktot = 0.0;
-        // with few photons left in the wave a pass need not wait for many
-        // flights: the threshold shrinks with the number of live lanes
-        const int live = __popcll(__ballot(have));
-        const int quarter = (live + 3) >> 2;
-        const int stop_below = (march_min < quarter) ? march_min : quarter;
-        for (;;) {
-            if (moving) {
-                const int st = march_step<R>(*J, p, cr, xloc, ktot, lc);
-                if (st != kCrossed) {
-                    moving = false;
-                    event = st == kEvent;
+            if constexpr (SINGLE) {
+                // one job: its seed, the generator key, is wave-uniform
+                p.rng.key.key0 = (uint32_t)J->seed;
+                p.rng.key.key1 = (uint32_t)(J->seed >> 32);
+            }
+            bool event = false;
+            R xloc = R(0);
+            double ktot = 0.0;
+            // with few photons left in the wave a pass need not wait for many
+            // flights: the threshold shrinks with the number of live lanes
+            const int live = __popcll(__ballot(have));
+            const int quarter = (live + 3) >> 2;
+            const int stop_below = (march_min < quarter) ? march_min : quarter;
+            for (;;) {
+                if (moving) {
+                    const int st = march_step<R>(*J, p, cr, xloc, ktot, lc);
+                    if (st != kCrossed) {
+                        moving = false;
+                        event = st == kEvent;
+                    }
+                }
+                const int in_flight = __popcll(__ballot(moving));
+                if (in_flight == 0 || in_flight < stop_below) break;
+            }
+            bool hi = false;
+            UparReq<R> q;
+            q.regime = UPAR_GAUSS;
+            uint64_t B0 = 0;
+            if (event) {
+                if (interact<R, CAMS>(*J, p, cr, xloc, ktot, pq, lc)) {
+                    hi = true;
+                    q = upar_setup<R>(cr.a, xloc, cr.xcw);
+                    B0 = p.rng.align();
+                } else if (p.status == 0) {
+                    moving = true;                    // dust scattering: a new flight
                 }
             }
-            const int in_flight = __popcll(__ballot(moving));
-            if (in_flight == 0 || in_flight < stop_below) break;
-        }
-        bool hi = false;
-        UparReq<R> q;
-        q.regime = UPAR_GAUSS;
-        uint64_t B0 = 0;
-        if (event) {
-            if (interact<R, CAMS>(*J, p, cr, xloc, ktot, lc)) {
-                hi = true;
-                q = upar_setup<R>(cr.a, xloc, cr.xcw);
-                B0 = p.rng.align();
-            } else if (p.status == 0) {
-                moving = true;                    // dust scattering: a new flight
+            R u = R(0);
+            uint32_t tacc = 0;
+            bool ok = true;
+            const uint32_t rounds = coop_upar<R, SINGLE>(hi && q.regime != UPAR_GAUSS, q, p.rng.key, B0, u,
+                                                 tacc, ok, s_slots[wave], s_table[wave],
+                                                 s_first[wave]);
+            if (lane == 0 && J) {
+                lc.add(C_ROUNDS, rounds);
+                lc.add(C_PASSES);
+            }
+            if (hi) {
+                if (q.regime == UPAR_GAUSS) {
+                    u = upar_gauss<R>(q, p.rng.key, B0);
+                    p.rng.k += Rng<R>::kPerBlock;
+                } else {
+                    lc.add(C_UPAR_TRIES, tacc + 1);
+                    p.rng.k += upar_advance<R>(q.regime, tacc);
+                    if (!ok) p.status = 3;
+                }
+                if (p.status == 0) {
+                    scatter_finish<R, CAMS>(*J, p, cr, xloc, (xloc < R(0)) ? -u : u, pq, lc);
+                    moving = true;
+                }
+            }
+            if (have && p.status != 0) {
+                finish<R>(*J, p, lc);
+                have = false;
+                moving = false;
             }
         }
-        R u = R(0);
-        uint32_t tacc = 0;
-        bool ok = true;
-        const uint32_t rounds = coop_upar<R, SINGLE>(hi && q.regime != UPAR_GAUSS, q, p.rng.key, B0, u,
-                                             tacc, ok, s_slots[wave], s_table[wave],
-                                             s_first[wave]);
-        if (lane == 0 && J) {
-            lc.add(C_ROUNDS, rounds);
-            lc.add(C_PASSES);
-        }
-        if (hi) {
-            if (q.regime == UPAR_GAUSS) {
-                u = upar_gauss<R>(q, p.rng.key, B0);
-                p.rng.k += Rng<R>::kPerBlock;
-            } else {
-                lc.add(C_UPAR_TRIES, tacc + 1);
-                p.rng.k += upar_advance<R>(q.regime, tacc);
-                if (!ok) p.status = 3;
+        if constexpr (CAMS) {
+            // Deferred peel-off marches: the lanes of the wave take the newest
+            // tasks and step them while a quarter of them (at most march_min)
+            // are still going; the rest wait in the queue.  Once the wave has
+            // no photons left and nothing more to take, it finishes every task
+            // before it leaves.
+            wave_lds_sync();
+            const bool last = drained && !__any(have);
+            int n = *pq.count;
+            n = (n < kPeelSlots) ? n : kPeelSlots;
+            while (n > 0) {
+                const int take = (n < 64) ? n : 64;
+                const int base = n - take;
+                bool act = lane < take;
+                PeelTask<R> t;
+                if (act) t = pq.slots[base + lane];
+                const JobView *Jt = SINGLE ? L.jobs : &L.jobs[act ? t.job : 0];
+                wave_lds_sync();
+                const int quarter = (take + 3) >> 2;
+                const int stop_below = last ? 1 : ((march_min < quarter) ? march_min : quarter);
+                for (;;) {
+                    if (act) {
+                        const int st = peel_step<R>(*Jt, t, lc);
+                        if (st != 0) {
+                            act = false;
+                            if (st == 1)
+                                peel_tally(*Jt, t.cam, t.bin, t.pix,
+                                           ((uint64_t)t.id1 << 32) | t.id0,
+                                           (double)t.W * ::exp(-t.tau));
+                        }
+                    }
+                    const int going = __popcll(__ballot(act));
+                    if (going == 0 || going < stop_below) break;
+                }
+                const uint64_t keep = __ballot(act);
+                if (act) pq.slots[base + __popcll(keep & lane_lt)] = t;
+                n = base + __popcll(keep);
+                wave_lds_sync();
+                if (!last && n <= kPeelSlots / 2) break;
             }
-            if (p.status == 0) {
-                scatter_finish<R, CAMS>(*J, p, cr, xloc, (xloc < R(0)) ? -u : u, lc);
-                moving = true;
-            }
-        }
-        if (have && p.status != 0) {
-            finish<R>(*J, p, lc);
-            have = false;
-            moving = false;
-        }
+            if (lane == 0) *pq.count = n;
+            wave_lds_sync();
         }
         if (!any_have && drained) break;
     }
