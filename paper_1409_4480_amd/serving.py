@@ -5,12 +5,16 @@ seconds) are admitted in arrival order while their device footprint fits the
 memory budget; every admitted job keeps its grid and tallies resident.  The
 server then runs epochs: one persistent transport launch over the next slice
 of photons of every active job (``colt_transport`` with ``photons_per_job``),
-so jobs that arrive while others are running join at the next epoch boundary
-and share the device with them.  A job's latency runs from its arrival to its
-tallies being on the host.
+so jobs that arrive while others are running join at the next epoch and share
+the device with them.  Up to ``depth`` epochs are in flight on separate
+streams, so an epoch's last long-lived photons share the device with the next
+epoch instead of holding it alone (a job's slices cover disjoint photon ids and
+its tallies are atomic, so overlapping epochs are safe).  A job's latency runs
+from its arrival to its tallies being on the host.
 
 Scheduling only: all transport work happens in the HIP library.
 """
+import ctypes
 import time
 from collections import deque
 
@@ -49,7 +53,7 @@ class Server:
     """
 
     def __init__(self, budget_bytes=None, epoch_photons=1 << 20, min_quota=8192,
-                 precision=colt.FP32_BULK, record=False, block=0, blocks_per_cu=0):
+                 precision=colt.FP32_BULK, record=False, block=0, blocks_per_cu=0, depth=2):
         import torch
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
@@ -61,7 +65,8 @@ class Server:
         self.record = record
         self.block = block
         self.blocks_per_cu = blocks_per_cu
-        self._sync = torch.cuda.current_stream().synchronize
+        self.depth = max(1, int(depth))
+        self._torch = torch
 
     def run(self, workloads, realtime=True):
         """Serves the jobs; returns one result dict per job, in input order.
@@ -74,8 +79,11 @@ class Server:
         for i in order:
             if footprint(workloads[i], self.record) > self.budget:
                 raise colt.ColtError(f"job {i} needs more than the memory budget")
+        torch = self._torch
+        streams = [torch.cuda.Stream() for _ in range(self.depth)]
         results = [None] * len(workloads)
         active = []
+        inflight = deque()             # (event, ids of the jobs in that epoch)
         used = 0
         epochs = 0
         self.max_active = 0
@@ -99,20 +107,33 @@ class Server:
                 used += need
                 self.max_used = max(self.max_used, used)
                 active.append(a)
-            if not active:
+            self.max_active = max(self.max_active, len(active))
+            ready = [a for a in active if a.job.status()[0] < a.job.status()[1]]
+            if ready and len(inflight) < self.depth:
+                quota = max(self.min_quota, self.epoch_photons // len(ready))
+                st = streams[epochs % self.depth]
+                st.wait_stream(torch.cuda.current_stream())     # the jobs' uploads
+                colt.transport([a.job for a in ready], photons_per_job=quota, block=self.block,
+                               blocks_per_cu=self.blocks_per_cu,
+                               stream=ctypes.c_void_p(st.cuda_stream))
+                ev = torch.cuda.Event()
+                ev.record(st)
+                inflight.append((ev, {id(a) for a in ready}))
+                epochs += 1
+                continue
+            if inflight:
+                inflight.popleft()[0].synchronize()
+            elif not active:
                 nxt = workloads[pending[0]].get("arrival", 0.0)
                 time.sleep(max(0.0, min(nxt - (time.perf_counter() - t0), 0.05)))
                 continue
-            self.max_active = max(self.max_active, len(active))
-            quota = max(self.min_quota, self.epoch_photons // len(active))
-            colt.transport([a.job for a in active], photons_per_job=quota, block=self.block,
-                           blocks_per_cu=self.blocks_per_cu)
-            self._sync()
-            epochs += 1
+            busy = set()
+            for _, ids in inflight:
+                busy |= ids
             still = []
             for a in active:
                 launched, total = a.job.status()
-                if launched < total:
+                if launched < total or id(a) in busy:
                     still.append(a)
                     continue
                 out = a.job.tally(wait=True)
