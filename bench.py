@@ -136,34 +136,51 @@ def serve_section(n_jobs):
             "speedup_batched_vs_serial_fp64": batched["scatterings_per_s"] / (scat / serial)}
 
 
-def camera_section(n_photons=262144, cap=2000):
-    """Peel-off throughput on the camera workloads: the 128^3 first-galaxy halo
-    (8 cameras, 256^2 images, 1000 bins) and the ~2e6-leaf NFW octree (4
-    cameras, 512^2 images), a full photon pool each, every photon followed for
-    its first `cap` events -- the steady state of those jobs, whose full
-    histories run to ~1e6 scatterings per photon."""
+def workloads_section(n_photons=262144, cap=2000):
+    """Throughput of the other workloads, a full photon pool each, FP32-bulk:
+    the 128^3 first-galaxy halo (8 cameras, 256^2 images, 1000 bins), the ~2e6-
+    leaf NFW octree (4 cameras, 512^2 images, non-local core-skipping estimate
+    at set-up) and an idealised first-galaxy model (WL7 on an octree, six axis
+    cameras), every photon followed for its first `cap` events -- the steady
+    state of jobs whose full histories run to ~1e6 scatterings per photon --
+    and the static slab at tau0 = 1e7 run to completion."""
+    import numpy as np
     import torch
 
-    from paper_1409_4480_amd import colt, inputs
+    from paper_1409_4480_amd import colt, galaxy, inputs
 
+    cases = [("halo_128cube_8cams", lambda: inputs.halo(n_photons=n_photons), cap),
+             ("nfw_octree_2e6_leaves_4cams", lambda: inputs.nfw_octree(n_photons=n_photons), cap),
+             ("galaxy_WL7_octree_6cams",
+              lambda: galaxy.Model("WL7").workload(n_photons=n_photons, npix=128, base_level=4,
+                                                   max_extra=5, factors=(16, 8, 16, 128)), cap),
+             ("slab_tau1e7", lambda: inputs.slab(tau0=1.0e7, n_photons=n_photons), 0)]
     out = {}
-    for name, wl in (("halo_128cube_8cams", inputs.halo(n_photons=n_photons)),
-                     ("nfw_octree_2e6_leaves_4cams", inputs.nfw_octree(n_photons=n_photons))):
-        wl["params"]["max_events"] = cap
+    for name, make, ev_cap in cases:
+        wl = make()
+        if ev_cap:
+            wl["params"]["max_events"] = ev_cap
+        torch.cuda.synchronize()
+        t = time.perf_counter()
         grid = colt.Grid(wl["grid"])
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t) * 1e3
         for rep in range(2):
             job = colt.Job(grid, wl["source"], wl["params"], precision=colt.FP32_BULK,
-                           max_events=cap)
+                           max_events=ev_cap)
             torch.cuda.synchronize()
             colt.transport([job], time_kernel=True)
             c = job.tally(wait=True)["counters"]
             ms = colt.last_kernel_ms()
             job.release()
         grid.release()
+        n_cells = int(np.asarray(wl["grid"]["n_HI"]).size)
         out[name] = {"scatterings_per_s": c["scat_hi"] / (ms * 1e-3), "kernel_ms": ms,
-                     "photons": n_photons, "events_cap": cap,
+                     "photons": n_photons, "events_cap": ev_cap or None,
+                     "scatterings_per_photon": c["scat_hi"] / max(c["emitted"], 1),
                      "peels_per_scattering": c["peels"] / max(c["scat_hi"], 1),
                      "peel_crossings_per_s": c["peel_crossings"] / (ms * 1e-3),
+                     "grid_nodes": n_cells, "grid_setup_ms": setup_ms,
                      "precision": "FP32-bulk"}
     return out
 
@@ -182,7 +199,7 @@ def main():
                     help="jobs of the workload fused in one launch for the batched figure "
                          "(0 or 1 skips it)")
     ap.add_argument("--no-cams", action="store_true",
-                    help="skip the camera (peel-off) workloads")
+                    help="skip the other workloads (cameras, octrees, galaxy model, slab)")
     ap.add_argument("--serve-jobs", type=int, default=48,
                     help="jobs in the serving stream (0 skips the serving section)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -190,7 +207,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the transport "
-              "shards by photon ranges across GPUs, which this build does not run.",
+              "shards by photon ranges across GPUs, which is not implemented here.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -304,7 +321,7 @@ def main():
         result["speedup_mixed_vs_fp64"] = value / (scat64 / el64)
     grid.release()
     if not args.no_cams:
-        result["cameras"] = camera_section()
+        result["workloads"] = workloads_section()
     if args.serve_jobs > 0:
         result["serving"] = serve_section(args.serve_jobs)
         result["latency_ms"] = {"p50": result["serving"]["poisson"]["p50_ms"],
