@@ -1,0 +1,92 @@
+"""Limits of the library on the GPU: the most jobs of a serving stream in one
+launch, the most cameras a job may have, and a large Cartesian grid.
+
+Every photon's stream depends only on (seed, id), so the FP64 history of each
+photon must not change with what else shares its launch; cameras are checked
+photon by photon against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_4480_amd import colt, inputs
+from tests.test_gpu_parity import compare_records, say
+
+pytestmark = pytest.mark.gpu
+
+PC = inputs.PC
+
+
+def test_512_jobs_in_one_launch_equal_each_job_alone():
+    """The serving stream's 512 jobs (here small spheres of several sizes and
+    depths) fused in one persistent launch: per-job queues, a binary search
+    over 513 prefix entries, counters and tallies per job."""
+    n_jobs = 512
+    rng = np.random.default_rng(512)
+    wls = []
+    for j in range(n_jobs):
+        n = int(rng.choice([4, 6, 8]))
+        wls.append(inputs.static_sphere(n=n, tau0=float(10 ** rng.uniform(2, 3.5)),
+                                        n_photons=int(rng.integers(1, 40)), seed=9000 + j,
+                                        isotropic=bool(j & 1), v_max=float(rng.uniform(0, 50))))
+    say(f"[gpu] {n_jobs} jobs, {sum(w['params']['n_photons'] for w in wls)} photons, one launch")
+    grids = [colt.Grid(w["grid"]) for w in wls]
+    jobs = [colt.Job(g, w["source"], w["params"], record=True) for g, w in zip(grids, wls)]
+    colt.transport(jobs)
+    fused = [j.tally() for j in jobs]
+    for j in jobs:
+        j.release()
+    for g in grids:
+        g.release()
+    for k in rng.choice(n_jobs, 24, replace=False):
+        alone = colt.run(wls[k], record=True)
+        for key in alone["records"]:
+            assert np.array_equal(alone["records"][key], fused[k]["records"][key]), (k, key)
+        # event counts are properties of the histories (the loop's pass and
+        # sampler-round counts describe the launch instead)
+        for name, v in alone["counters"].items():
+            if name not in ("passes", "upar_rounds"):
+                assert v == fused[k]["counters"][name], (k, name)
+    assert all(f["counters"]["emitted"] == w["params"]["n_photons"]
+               for f, w in zip(fused, wls))
+
+
+def test_64_cameras_match_the_oracle():
+    """A job with the largest camera count: 64 directions on a spiral."""
+    m = 64
+    i = np.arange(m) + 0.5
+    z = 1 - 2 * i / m
+    phi = np.pi * (1 + 5 ** 0.5) * i
+    cams = np.stack([np.sqrt(1 - z * z) * np.cos(phi), np.sqrt(1 - z * z) * np.sin(phi), z], 1)
+    wl = inputs.static_sphere(n=8, tau0=3e2, n_photons=64, seed=64, isotropic=False,
+                              recoil=True, cameras=cams, cam_nbins=50, cam_npix=4)
+    say("[gpu] 64 cameras, 64 photons")
+    g = colt.run(wl, record=True)
+    r = oracle.run(wl["grid"], wl["source"], wl["params"], records=True)
+    compare_records(g, r, 2 * PC, peel=True)
+    assert g["records"]["peel"].shape == (64, m)
+    # every camera sees the same sphere: the per-camera sums agree to noise
+    tot = g["cam_spec"].sum(axis=1) / 64
+    assert np.all(np.abs(tot - tot.mean()) < 0.5 * tot.mean())
+    cams65 = np.vstack([cams, cams[:1]])
+    bad = inputs.static_sphere(n=8, tau0=3e2, n_photons=1, cameras=cams65, cam_nbins=50,
+                               cam_npix=4)
+    grid = colt.Grid(bad["grid"])
+    with pytest.raises(colt.ColtError):
+        colt.Job(grid, bad["source"], bad["params"])
+    grid.release()
+
+
+def test_large_cartesian_grid():
+    """A 256^3 grid (16.8e6 cells, ~2 GB of cell records) holding the 64^3 dusty
+    sphere's gas at four times the resolution: the same physical problem, so the
+    escape fraction agrees with the 64^3 run within Monte-Carlo noise."""
+    n = 100_000
+    say("[gpu] 256^3 dusty sphere, FP32-bulk")
+    big = colt.run(inputs.dusty_sphere(n=256, n_photons=n, seed=256), precision=colt.FP32_BULK)
+    small = colt.run(inputs.dusty_sphere(n=64, n_photons=n, seed=256), precision=colt.FP32_BULK)
+    fb, fs = big["counters"]["escaped"] / n, small["counters"]["escaped"] / n
+    se = np.sqrt((fb * (1 - fb) + fs * (1 - fs)) / n)
+    assert abs(fb - fs) < 4 * se
+    assert big["counters"]["emitted"] == n == big["counters"]["escaped"] + \
+        big["counters"]["absorbed"]
