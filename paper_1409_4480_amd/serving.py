@@ -122,7 +122,13 @@ class Server:
                 epochs += 1
                 continue
             if inflight:
-                inflight.popleft()[0].synchronize()
+                # wait for an epoch to end, or for the next arrival to admit it
+                while not any(e.query() for e, _ in inflight):
+                    if realtime and pending and \
+                            time.perf_counter() - t0 >= workloads[pending[0]].get("arrival", 0.0):
+                        break
+                    time.sleep(2e-4)
+                inflight = deque(x for x in inflight if not x[0].query())
             elif not active:
                 nxt = workloads[pending[0]].get("arrival", 0.0)
                 time.sleep(max(0.0, min(nxt - (time.perf_counter() - t0), 0.05)))
