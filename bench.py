@@ -136,6 +136,48 @@ def serve_section(n_jobs):
             "speedup_batched_vs_serial_fp64": batched["scatterings_per_s"] / (scat / serial)}
 
 
+def precision_errors(grid, wl):
+    """FP32-bulk against FP64 on the same job (same seed), per result: escape
+    fraction, mean and mean |x| of the escaped photons, mean scatterings per
+    photon -- each as the difference and its Monte-Carlo standard error --
+    and the escape spectra's two-sample chi^2 and x KS p-values.  The two
+    modes draw different histories from the same streams, so agreement is
+    statistical."""
+    import numpy as np
+    from scipy import stats as sst
+
+    from paper_1409_4480_amd import colt
+
+    out = {}
+    for prec in (colt.FP32_BULK, colt.FP64):
+        job = colt.Job(grid, wl["source"], wl["params"], precision=prec, record=True)
+        colt.transport([job])
+        out[prec] = job.tally(wait=True)
+        job.release()
+    a, b = out[colt.FP32_BULK], out[colt.FP64]
+    n = wl["params"]["n_photons"]
+    res = {}
+    fa, fb = a["counters"]["escaped"] / n, b["counters"]["escaped"] / n
+    res["escape_fraction"] = {"fp32": fa, "fp64": fb, "diff": fa - fb,
+                              "sigma": math.sqrt((fa * (1 - fa) + fb * (1 - fb)) / n)}
+    xa = a["records"]["x"][a["records"]["status"] == 1]
+    xb = b["records"]["x"][b["records"]["status"] == 1]
+    for name, fa_, fb_ in (("mean_x", xa, xb), ("mean_abs_x", np.abs(xa), np.abs(xb))):
+        res[name] = {"fp32": float(fa_.mean()), "fp64": float(fb_.mean()),
+                     "diff": float(fa_.mean() - fb_.mean()),
+                     "sigma": float(math.sqrt(fa_.var() / len(fa_) + fb_.var() / len(fb_)))}
+    na, nb = a["records"]["nscat"], b["records"]["nscat"]
+    res["mean_scatterings"] = {"fp32": float(na.mean()), "fp64": float(nb.mean()),
+                               "diff": float(na.mean() - nb.mean()),
+                               "sigma": float(math.sqrt((na.var() + nb.var()) / n))}
+    ha, hb = a["spectrum"], b["spectrum"]
+    keep = (ha + hb) >= 10
+    table = np.vstack([ha[keep], hb[keep]])
+    res["spectrum_chi2_p"] = float(sst.chi2_contingency(table)[1])
+    res["escaped_x_ks_p"] = float(sst.ks_2samp(xa, xb).pvalue)
+    return res
+
+
 def workloads_section(n_photons=262144, cap=2000):
     """Throughput of the other workloads, a full photon pool each, FP32-bulk:
     the 128^3 first-galaxy halo (8 cameras, 256^2 images, 1000 bins), the ~2e6-
@@ -319,6 +361,7 @@ def main():
             "escaped_fraction": sum(c["escaped"] for c in cnt64) /
             sum(c["emitted"] for c in cnt64)}
         result["speedup_mixed_vs_fp64"] = value / (scat64 / el64)
+        result["fp32_vs_fp64"] = precision_errors(grid, wl)
     grid.release()
     if not args.no_cams:
         result["workloads"] = workloads_section()
