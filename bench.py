@@ -323,8 +323,9 @@ def main():
                      "loop_passes": sum(c["passes"] for c in cnt) / args.steps,
                      "upar_rounds_per_pass": sum(c["upar_rounds"] for c in cnt) /
                      max(sum(c["passes"] for c in cnt), 1),
+                     # FP32 lanes evaluate two candidates per round
                      "upar_candidate_lane_use": sum(c["upar_tries"] for c in cnt) /
-                     max(64 * sum(c["upar_rounds"] for c in cnt), 1)},
+                     max(128 * sum(c["upar_rounds"] for c in cnt), 1)},
         "grid_setup_ms": grid_setup_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
