@@ -1,12 +1,14 @@
 // HIP kernels of the Lyman-alpha transport library (gfx950).
 //
 //  k_cell_setup   per-cell line quantities from (n_HI, T, v, k_dust)
+//  k_nonlocal     per-cell non-local a*tau estimate (six axis paths)
 //  k_transport    persistent photon-pool transport: each lane carries one
 //                 photon through emission, cell-by-cell ray tracing,
 //                 scattering and next-event tallies; a lane whose photon has
 //                 escaped or been absorbed takes the next photon from a shared
-//                 queue (one atomic per wave per refill).
-//  k_voigt, k_sample   device checks of H(a,x) and of the samplers.
+//                 queue (one atomic per wave per refill)
+//  k_plan, k_advance   device-side slicing of jobs for graph replays
+//  k_voigt, k_sample   device checks of H(a,x) and of the samplers
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
