@@ -800,6 +800,14 @@ __device__ __forceinline__ void wave_lds_sync()
 
 constexpr uint32_t kMaxUparRounds = 1u << 22;   // bound on rounds; never reached in practice
 
+// n / m for 0 <= n < 256 and 1 <= m <= 64 through the reciprocal of m:
+// (n + 1/2) / m stays at least 1/(2m) from an integer, far more than the
+// rounding of the product, so the truncation is exact.
+__device__ __forceinline__ uint32_t small_div(uint32_t n, float inv_m)
+{
+    return (uint32_t)(((float)n + 0.5f) * inv_m);
+}
+
 // All 64 lanes of the wave must call this together.  On return, lanes with
 // `need` hold the unsigned |u_par| in u and the accepted candidate number in t
 // (ok = false only if the round bound was hit).  KEY_UNIFORM: every lane's
@@ -827,14 +835,15 @@ __device__ __forceinline__ uint32_t coop_upar(bool need, const UparReq<R> &q, co
         if (S == 0) break;
         ++rounds;
         const int m = __popcll(S);
+        const float inv_m = __builtin_amdgcn_rcpf((float)m);
         const int rank = __popcll(S & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
         if (need) {
             table[rank] = lane;
             first[rank] = 64u;
         }
         wave_lds_sync();
-        const int rr = lane % m;
-        const uint32_t ss = (uint32_t)(lane / m);
+        const uint32_t ss = small_div((uint32_t)lane, inv_m);
+        const int rr = lane - (int)ss * m;
         const UparSlot<R> s = slots[table[rr]];
         UparReq<R> qq;
         qq.X = s.X; qq.a = s.a; qq.u0 = s.u0; qq.p = s.p; qq.th0 = s.th0; qq.regime = s.regime;
@@ -868,11 +877,11 @@ __device__ __forceinline__ uint32_t coop_upar(bool need, const UparReq<R> &q, co
         if (need) {
             if (f < 64u) {
                 u = got;
-                const uint32_t unit = base + f / (uint32_t)m;
+                const uint32_t unit = base + small_div(f, inv_m);
                 t = (sizeof(R) == 8) ? unit : 2u * unit + got_half;
                 need = false;
             } else {
-                base += (uint32_t)((64 - rank + m - 1) / m);
+                base += small_div((uint32_t)(64 - rank + m - 1), inv_m);
                 slots[lane].base = base;
                 if (round >= kMaxUparRounds) { need = false; ok = false; u = R(0); t = base; }
             }
