@@ -416,6 +416,7 @@ struct PeelQueue {
     PeelTask<R> *slots;       // the wave's kPeelSlots tasks
     int *count;               // tasks posted; beyond kPeelSlots the lane ran them itself
     int job;                  // the lane's job index in the launch
+    const double *cams;       // its camera table (an LDS copy in single-job launches)
 };
 
 // W exp(-tau) of camera `cam` into its spectrum bin and image pixel (and the
@@ -433,9 +434,10 @@ __device__ __forceinline__ void peel_tally(const JobView &J, int cam, int bin, i
 // Returns 0 when it goes on in the next cell, 1 at the domain edge (tally), 2
 // above the cut-off (no contribution).
 template <typename R>
-__device__ __forceinline__ int peel_step(const JobView &J, PeelTask<R> &t, LaneCounters &lc)
+__device__ __forceinline__ int peel_step(const JobView &J, const double *cams, PeelTask<R> &t,
+                                         LaneCounters &lc)
 {
-    const double *cam = J.cam + 12 * t.cam;
+    const double *cam = cams + 12 * t.cam;
     const double d[3] = {cam[0], cam[1], cam[2]};
     const double id[3] = {cam[3], cam[4], cam[5]};
     const R dr[3] = {(R)cam[0], (R)cam[1], (R)cam[2]};
@@ -472,7 +474,7 @@ __device__ __forceinline__ void peel_off(const JobView &J, const Photon<R> &p,
     using F = Fn<R>;
     const R wn = R(1) + F::div(ps.rW, R(3));
     for (int i = 0; i < J.n_cams; ++i) {
-        const double *cam = J.cam + 12 * i;
+        const double *cam = pq.cams + 12 * i;
         const double d[3] = {cam[0], cam[1], cam[2]};
         const double id[3] = {cam[3], cam[4], cam[5]};
         const R dr[3] = {(R)cam[0], (R)cam[1], (R)cam[2]};
@@ -931,10 +933,19 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
     const int lane = threadIdx.x & 63;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + wave) & (kCounterSlots - 1));
+    __shared__ double s_cam[(CAMS && SINGLE) ? 12 * kMaxCams : 1];
     PeelQueue<R> pq;
     pq.slots = s_peel[CAMS ? wave : 0];
     pq.count = &s_peel_n[wave];
     pq.job = 0;
+    pq.cams = nullptr;
+    if constexpr (CAMS && SINGLE) {
+        // the job's camera table, read at every peel-off step, kept in LDS
+        for (int i = threadIdx.x; i < 12 * L.jobs->n_cams; i += blockDim.x)
+            s_cam[i] = L.jobs->cam[i];
+        pq.cams = s_cam;
+        __syncthreads();
+    }
     if (lane == 0) s_peel_n[wave] = 0;
     wave_lds_sync();
     Photon<R> p;
@@ -975,7 +986,10 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
                             }
                             id = L.first_id[j] + (g - L.prefix[j]);
                         }
-                        if constexpr (!SINGLE) pq.job = (int)(J - L.jobs);
+                        if constexpr (!SINGLE) {
+                            pq.job = (int)(J - L.jobs);
+                            pq.cams = J->cam;
+                        }
                         emit<R, CAMS>(*J, p, id, cr, pq, lc);
                         have = true;
                         moving = true;
@@ -1079,7 +1093,7 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
                 const int stop_below = last ? 1 : ((march_min < quarter) ? march_min : quarter);
                 for (;;) {
                     if (act) {
-                        const int st = peel_step<R>(*Jt, t, lc);
+                        const int st = peel_step<R>(*Jt, SINGLE ? s_cam : Jt->cam, t, lc);
                         if (st != 0) {
                             act = false;
                             if (st == 1)
