@@ -62,6 +62,28 @@ struct RngKey {
         philox4x32_10(c0, c1, c2, c3, key0, key1);
         w0 = c0; w1 = c1; w2 = c2; w3 = c3;
     }
+    // blocks b and b + 1 as two independent chains, so that their rounds
+    // overlap instead of following each other
+    __device__ __forceinline__ void block2(uint64_t b, uint32_t a[4], uint32_t c[4]) const
+    {
+        const uint64_t b1 = b + 1;
+        a[0] = (uint32_t)b; a[1] = (uint32_t)(b >> 32); a[2] = id0; a[3] = id1;
+        c[0] = (uint32_t)b1; c[1] = (uint32_t)(b1 >> 32); c[2] = id0; c[3] = id1;
+        uint32_t k0 = key0, k1 = key1;
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            const uint64_t pa0 = (uint64_t)0xD2511F53u * a[0], pa1 = (uint64_t)0xCD9E8D57u * a[2];
+            const uint64_t pc0 = (uint64_t)0xD2511F53u * c[0], pc1 = (uint64_t)0xCD9E8D57u * c[2];
+            const uint32_t na0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa1 >> 32), a[1], k0, 0x96);
+            const uint32_t na2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa0 >> 32), a[3], k1, 0x96);
+            const uint32_t nc0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pc1 >> 32), c[1], k0, 0x96);
+            const uint32_t nc2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pc0 >> 32), c[3], k1, 0x96);
+            a[1] = (uint32_t)pa1; a[3] = (uint32_t)pa0; a[0] = na0; a[2] = na2;
+            c[1] = (uint32_t)pc1; c[3] = (uint32_t)pc0; c[0] = nc0; c[2] = nc2;
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+    }
 };
 
 template <typename R>
@@ -125,6 +147,23 @@ struct Rng<float> {
         ++k;
         return u32f(w);
     }
+    // the next five draws; from a block boundary the two blocks they span are
+    // generated together and the second one's last three words stay cached
+    __device__ __forceinline__ void next5(float u[5])
+    {
+        if (((uint32_t)k & 3u) == 0) {
+            uint32_t a[4], c[4];
+            key.block2(k >> 2, a, c);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) u[i] = u32f(a[i]);
+            u[4] = u32f(c[0]);
+            w1 = c[1]; w2 = c[2]; w3 = c[3];
+            k += 5;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) u[i] = next();
+        }
+    }
     __device__ __forceinline__ uint64_t align()
     {
         k = (k + 3) & ~(uint64_t)3;
@@ -169,7 +208,9 @@ struct Fn<float> {
     {
         return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
     }
-    static __device__ __forceinline__ float sqrt(float x) { return __builtin_sqrtf(x); }
+    // the square-root unit alone (about 1 ulp; the correctly rounded sqrtf
+    // wraps it in a scaling and two-sided correction, ~6x its latency)
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     // x >= 0: 2^(log2(x) / 3) on the transcendental unit (a few ulp)
     static __device__ __forceinline__ float cbrt(float x)
     {
@@ -416,11 +457,9 @@ __device__ __forceinline__ R draw_upar(R a, R x, R xcw, Rng<R> &rng, uint32_t &t
 // Perpendicular components: Box-Muller on exp(-u^2)/sqrt(pi), truncated below
 // the core-skipping frequency (Sec. 3.2.4).
 template <typename R>
-__device__ __forceinline__ void draw_uperp(R xc, Rng<R> &rng, R &u1, R &u2)
+__device__ __forceinline__ void draw_uperp_from(R xc, R R1, R R2, R &u1, R &u2)
 {
     using F = Fn<R>;
-    const R R1 = rng.next();
-    const R R2 = rng.next();
     const R rho = F::sqrt(xc * xc - F::log(R1));
     R c, s;
     F::cossin2pi(R2, c, s);
@@ -428,13 +467,20 @@ __device__ __forceinline__ void draw_uperp(R xc, Rng<R> &rng, R &u1, R &u2)
     u2 = rho * s;
 }
 
+template <typename R>
+__device__ __forceinline__ void draw_uperp(R xc, Rng<R> &rng, R &u1, R &u2)
+{
+    const R R1 = rng.next();
+    const R R2 = rng.next();
+    draw_uperp_from<R>(xc, R1, R2, u1, u2);
+}
+
 // Cosine of the scattering angle for W(mu) ~ 1 + rW mu^2 (eq. phaseW) by
 // inverting its cubic CDF with Cardano's formula.
 template <typename R>
-__device__ __forceinline__ R draw_mu(R rW, Rng<R> &rng)
+__device__ __forceinline__ R draw_mu_from(R rW, R Rm)
 {
     using F = Fn<R>;
-    const R Rm = rng.next();
     if (rW == R(0)) return R(2) * Rm - R(1);
     const R p = F::div(R(3), rW);
     const R q = (R(1) + p) * (R(1) - R(2) * Rm);
@@ -446,6 +492,13 @@ __device__ __forceinline__ R draw_mu(R rW, Rng<R> &rng)
     mu = (mu > R(1)) ? R(1) : mu;
     mu = (mu < R(-1)) ? R(-1) : mu;
     return mu;
+}
+
+template <typename R>
+__device__ __forceinline__ R draw_mu(R rW, Rng<R> &rng)
+{
+    const R Rm = rng.next();
+    return draw_mu_from<R>(rW, Rm);
 }
 
 // Orthonormal e1, e2 perpendicular to unit k: e1 ~ k x z (k x x when |k_z| > 0.9).

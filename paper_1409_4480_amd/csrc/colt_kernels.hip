@@ -654,7 +654,10 @@ __device__ __forceinline__ int march_step(const JobView &J, Photon<R> &p, CellRe
         cr = load_cell<R>(J.g, p.c.cell);
         return kCrossed;
     }
-    const double l = p.tau / ktot;
+    // FP32: ktot holds single-precision opacities, so its reciprocal in
+    // single precision loses nothing a double division would keep
+    const double l = (sizeof(R) == 4) ? p.tau * (double)__builtin_amdgcn_rcpf((float)ktot)
+                                      : p.tau / ktot;
 #pragma unroll
     for (int d = 0; d < 3; ++d) p.r[d] += l * k[d];
     if (++p.events >= J.max_events || !(p.r[0] == p.r[0])) { p.status = 3; return kGone; }
@@ -708,17 +711,30 @@ __device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
     }
     const R axl = (xloc < R(0)) ? -xloc : xloc;
     if (axl >= xcw) xc = R(0);                 // already in the wing: no cut-off
+    // the scattering's draws in stream order: u_perp (2), mu, phi, next tau;
+    // FP32 takes all five at once (its two generator blocks overlap)
+    R dw[5] = {R(0), R(0), R(0), R(0), R(0)};
     R u1, u2;
-    draw_uperp<R>(xc, p.rng, u1, u2);
+    if constexpr (sizeof(R) == 4) {
+        p.rng.next5(dw);
+        draw_uperp_from<R>(xc, dw[0], dw[1], u1, u2);
+    } else {
+        draw_uperp<R>(xc, p.rng, u1, u2);
+    }
     R e1[3], e2[3];
     perp_basis<R>(p.kr, e1, e2);
     R ua[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) ua[d] = upar * p.kr[d] + u1 * e1[d] + u2 * e2[d];
     const R rW = J.isotropic ? R(0) : ((axl < xcw) ? R(3.0 / 11.0) : R(1));
-    const R mu = draw_mu<R>(rW, p.rng);
-    R cph, sph;
-    F::cossin2pi(p.rng.next(), cph, sph);
+    R mu, cph, sph;
+    if constexpr (sizeof(R) == 4) {
+        mu = draw_mu_from<R>(rW, dw[2]);
+        F::cossin2pi(dw[3], cph, sph);
+    } else {
+        mu = draw_mu<R>(rW, p.rng);
+        F::cossin2pi(p.rng.next(), cph, sph);
+    }
     const R st = F::sqrt(R(1) - mu * mu);
     R kf[3];
 #pragma unroll
@@ -747,7 +763,7 @@ __device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
     }
     set_dir(p, kf[0], kf[1], kf[2]);
     p.x = F::div(xf + (kf[0] * cr.ux + kf[1] * cr.uy + kf[2] * cr.uz), cr.s);
-    p.tau = -(double)F::log(p.rng.next());
+    p.tau = -(double)F::log((sizeof(R) == 4) ? dw[4] : p.rng.next());
 }
 
 template <typename R>
