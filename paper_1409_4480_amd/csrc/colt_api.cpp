@@ -691,7 +691,7 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
             }
             HIP_TRY(hipEventRecord(g_t0, s));
         }
-        HIP_TRY(launch_transport(prec, cams, L, (int)grid, block, s));
+        HIP_TRY(launch_transport(prec, cams, L, nj == 1 ? views[0] : JobView{}, (int)grid, block, s));
         if (timed) {
             HIP_TRY(hipEventRecord(g_t1, s));
             g_timed = true;
@@ -774,7 +774,8 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
     if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t e1 = launch_plan(P, false, s);
-        if (e1 == hipSuccess) e1 = launch_transport(prec, cams, L, grid, block, s);
+        if (e1 == hipSuccess)
+            e1 = launch_transport(prec, cams, L, nj == 1 ? jobs[0]->view : JobView{}, grid, block, s);
         if (e1 == hipSuccess) e1 = launch_plan(P, true, s);
         e = hipStreamEndCapture(s, &gr->graph);
         if (e1 != hipSuccess) e = e1;

@@ -786,7 +786,8 @@ __device__ __forceinline__ void finish(const JobView &J, const Photon<R> &p, Lan
         J.rec_nscat[id] = p.nscat;
         J.rec_status[id] = p.status;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) J.rec_pos[3 * id + d] = J.box_min_cm[d] + p.r[d] * J.dx_cm;
+        for (int d = 0; d < 3; ++d)        // one rounding in every kernel variant
+            J.rec_pos[3 * id + d] = ::fma(p.r[d], J.dx_cm, J.box_min_cm[d]);
     }
 }
 
@@ -927,8 +928,11 @@ __device__ __forceinline__ int find_job(const LaunchView &L, uint64_t g)
 // long flight does not hold the whole wave); the wave then serves all
 // parallel-velocity draws cooperatively and completes the scatterings.  A
 // photon's history does not depend on where the passes cut its flights.
-// SINGLE launches carry one job, whose parameters then live in scalar
-// registers.
+// SINGLE launches carry one job.  The FP32 kernels take it by value as J1:
+// its parameters are then kernel arguments, read through the scalar cache
+// (the job table in global memory is re-read with vector loads on every use).
+// The FP64 kernels, whose vector registers are full, keep reading the table:
+// scalar copies of the parameters push part of their photon state to scratch.
 // Resident workgroups of 256 lanes per CU the register allocation aims for.
 template <typename R, bool CAMS>
 constexpr int transport_min_blocks()
@@ -937,7 +941,7 @@ constexpr int transport_min_blocks()
 }
 
 template <typename R, bool CAMS, bool SINGLE>
-__global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_transport(LaunchView L)
+__global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_transport(LaunchView L, JobView J1)
 {
     __shared__ UparSlot<R> s_slots[4][64];
     __shared__ int32_t s_table[4][64];
@@ -971,7 +975,8 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
     lc.col = &s_counts[0][threadIdx.x];
 #pragma unroll
     for (int i = 0; i < kLaneCounters; ++i) s_counts[i][threadIdx.x] = 0ull;
-    const JobView *J = SINGLE ? L.jobs : nullptr;
+    const JobView *const J_single = (sizeof(R) == 4) ? &J1 : L.jobs;
+    const JobView *J = SINGLE ? J_single : nullptr;
     const uint64_t total = L.prefix[L.n_jobs];
     const int march_min = L.march_min;
     bool have = false, moving = false, drained = total == 0;
@@ -1103,7 +1108,7 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
                 bool act = lane < take;
                 PeelTask<R> t;
                 if (act) t = pq.slots[base + lane];
-                const JobView *Jt = SINGLE ? L.jobs : &L.jobs[act ? t.job : 0];
+                const JobView *Jt = SINGLE ? J_single : &L.jobs[act ? t.job : 0];
                 wave_lds_sync();
                 const int quarter = (take + 3) >> 2;
                 const int stop_below = last ? 1 : ((march_min < quarter) ? march_min : quarter);
@@ -1308,9 +1313,10 @@ hipError_t launch_cell_setup(int64_t n, const double *n_HI, const double *T, con
 }
 
 template <typename R, bool CAMS, bool SINGLE>
-static hipError_t launch_t(const LaunchView &L, int grid, int block, hipStream_t s)
+static hipError_t launch_t(const LaunchView &L, const JobView &J1, int grid, int block,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL((k_transport<R, CAMS, SINGLE>), dim3(grid), dim3(block), 0, s, L);
+    hipLaunchKernelGGL((k_transport<R, CAMS, SINGLE>), dim3(grid), dim3(block), 0, s, L, J1);
     return hipGetLastError();
 }
 
@@ -1321,20 +1327,20 @@ static hipError_t occupancy_t(int block, int *blocks_per_cu)
                                                         k_transport<R, CAMS, SINGLE>, block, 0);
 }
 
-hipError_t launch_transport(int precision, bool cams, const LaunchView &L, int grid, int block,
-                            hipStream_t s)
+hipError_t launch_transport(int precision, bool cams, const LaunchView &L, const JobView &J1,
+                            int grid, int block, hipStream_t s)
 {
     const bool single = L.n_jobs == 1;
     if (precision == 0) {
-        if (cams) return single ? launch_t<double, true, true>(L, grid, block, s)
-                                : launch_t<double, true, false>(L, grid, block, s);
-        return single ? launch_t<double, false, true>(L, grid, block, s)
-                      : launch_t<double, false, false>(L, grid, block, s);
+        if (cams) return single ? launch_t<double, true, true>(L, J1, grid, block, s)
+                                : launch_t<double, true, false>(L, J1, grid, block, s);
+        return single ? launch_t<double, false, true>(L, J1, grid, block, s)
+                      : launch_t<double, false, false>(L, J1, grid, block, s);
     }
-    if (cams) return single ? launch_t<float, true, true>(L, grid, block, s)
-                            : launch_t<float, true, false>(L, grid, block, s);
-    return single ? launch_t<float, false, true>(L, grid, block, s)
-                  : launch_t<float, false, false>(L, grid, block, s);
+    if (cams) return single ? launch_t<float, true, true>(L, J1, grid, block, s)
+                            : launch_t<float, true, false>(L, J1, grid, block, s);
+    return single ? launch_t<float, false, true>(L, J1, grid, block, s)
+                  : launch_t<float, false, false>(L, J1, grid, block, s);
 }
 
 hipError_t transport_occupancy(int precision, bool cams, bool single, int block,
