@@ -526,6 +526,7 @@ colt_status colt_emit(colt_grid g, const colt_source_desc *src, const colt_job_p
     v.isotropic = p->isotropic ? 1 : 0;
     v.n_bins = p->n_bins;
     v.xcrit_global = (p->atau0 < 1.0) ? 0.0 : std::cbrt(p->atau0) / 5.0;
+    v.xcrit_global_f = (float)v.xcrit_global;
     v.x_min = p->x_min;
     v.x_max = p->x_max;
     v.n_cams = nc;

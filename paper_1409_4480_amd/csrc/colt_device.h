@@ -289,6 +289,11 @@ struct UparReq {
     R p;          // probability of the part below u0
     R th0;        // FP64: theta0; FP32: phi0 = theta0 + pi/2
     int regime;
+    // FP32 only, fixed per request: the first word's split point p 2^32 and
+    // the reciprocal widths of the two parts' word ranges (the core regime is
+    // the lower part over all words, with phi0 = pi)
+    uint32_t wp;
+    float inv_lo, inv_hi;
 };
 
 template <typename R>
@@ -301,7 +306,13 @@ __device__ __forceinline__ UparReq<R> upar_setup(R a, R x, R xcw)
     q.u0 = R(0);
     q.p = R(0);
     q.th0 = R(0);
+    q.wp = 0xFFFFFFFFu;
+    q.inv_lo = 0x1.0p-32f;
+    q.inv_hi = 1.0f;
     q.regime = (q.X <= R(1)) ? UPAR_CORE : ((q.X < R(9)) ? UPAR_SPLIT : UPAR_GAUSS);
+    if constexpr (sizeof(R) == 4) {
+        if (q.regime == UPAR_CORE) q.th0 = float(kPi);
+    }
     if (q.regime == UPAR_SPLIT) {
         const R X = q.X;
         R u0;
@@ -319,6 +330,9 @@ __device__ __forceinline__ UparReq<R> upar_setup(R a, R x, R xcw)
             const float phi0 = F::atan(F::div(a, X - u0));
             q.th0 = phi0;
             q.p = F::div(phi0, phi0 + e0 * (float(kPi) - phi0));
+            q.wp = (q.p >= 1.0f) ? 0xFFFFFFFFu : (uint32_t)(q.p * 4294967296.0f);
+            q.inv_lo = __builtin_amdgcn_rcpf((float)q.wp);
+            q.inv_hi = __builtin_amdgcn_rcpf((float)(0u - q.wp));
         }
     }
     return q;
@@ -346,17 +360,13 @@ __device__ __forceinline__ bool upar_eval_fp32(const UparReq<float> &q, uint32_t
                                                uint32_t wb, float &u)
 {
     using F = Fn<float>;
-    float phi, bias = 0.0f;
-    if (q.regime == UPAR_CORE) {
-        phi = float(kPi) * u32f(wa);            // theta = pi (R - 1/2)
-    } else {
-        const uint32_t wp = (q.p >= 1.0f) ? 0xFFFFFFFFu : (uint32_t)(q.p * 4294967296.0f);
-        const bool lower = wa < wp;
-        const float Rth = F::div((float)(lower ? wa : wa - wp) + 0.5f,
-                                 (float)(lower ? wp : 0u - wp));
-        phi = lower ? Rth * q.th0 : q.th0 + Rth * (float(kPi) - q.th0);
-        if (!lower) bias = q.u0 * q.u0;
-    }
+    // one branch-free form for both regimes: a core request is the lower part
+    // over all words (wp = 2^32 - 1, width 2^-32, phi0 = pi), which gives
+    // phi = pi (R - 1/2) + pi/2 with R = u32f(wa) exactly
+    const bool lower = wa < q.wp;
+    const float Rth = ((float)(lower ? wa : wa - q.wp) + 0.5f) * (lower ? q.inv_lo : q.inv_hi);
+    const float phi = lower ? Rth * q.th0 : q.th0 + Rth * (float(kPi) - q.th0);
+    const float bias = lower ? 0.0f : q.u0 * q.u0;
     float c, s;
     F::cossin2pi(phi * float(0.5 / kPi), c, s);
     u = q.X - q.a * F::div(c, s);               // a tan(phi - pi/2) = -a cot(phi)

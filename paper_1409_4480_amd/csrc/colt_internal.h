@@ -55,6 +55,7 @@ struct JobView {
     uint64_t seed, n_photons, max_events;
     int32_t xcrit_mode, recoil, isotropic, n_bins;
     double xcrit_global;
+    float xcrit_global_f, pad1;     // the same in single precision (a scalar operand)
     double x_min, x_max;
     // next-event estimator (Sec. 6.1)
     int32_t n_cams, cam_nbins, npix, record;

@@ -703,7 +703,7 @@ __device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
     const R a = cr.a, xcw = cr.xcw;
     R xc = R(0);
     if (J.xcrit_mode == 1) {
-        xc = (R)J.xcrit_global;
+        xc = (sizeof(R) == 4) ? (R)J.xcrit_global_f : (R)J.xcrit_global;
     } else if (J.xcrit_mode == 2) {
         const CellAux<R> ax = load_aux<R>(J.g, p.c.cell);
         const R atau = a * cr.k0 * (R)min_face_distance(p.c, p.r) + ax.atau_nl;
@@ -802,12 +802,92 @@ __device__ __forceinline__ void finish(const JobView &J, const Photon<R> &p, Lan
 // exactly while all 64 lanes stay busy until the last request of the wave is
 // served.
 // ---------------------------------------------------------------------------
-template <typename R>
-struct UparSlot {
-    R X, a, u0, p, th0;
+// A request in LDS.  KU: the generator key is the same for every lane (one
+// job), so the slot need not hold it.
+template <typename R, bool KU>
+struct UparSlot;
+
+template <bool KU>
+struct UparSlot<double, KU> {
+    double X, a, u0, p, th0;
     int32_t regime;
     uint32_t key0, key1, id0, id1, b0lo, b0hi;
     uint32_t base;
+    __device__ __forceinline__ void put(const UparReq<double> &q, const RngKey &k)
+    {
+        X = q.X; a = q.a; u0 = q.u0; p = q.p; th0 = q.th0; regime = q.regime;
+        key0 = k.key0; key1 = k.key1; id0 = k.id0; id1 = k.id1;
+    }
+    __device__ __forceinline__ UparReq<double> req() const
+    {
+        UparReq<double> q;
+        q.X = X; q.a = a; q.u0 = u0; q.p = p; q.th0 = th0; q.regime = regime;
+        q.wp = 0u; q.inv_lo = 0.0f; q.inv_hi = 0.0f;
+        return q;
+    }
+    __device__ __forceinline__ RngKey key(const RngKey &uniform) const
+    {
+        RngKey k;
+        k.key0 = KU ? uniform.key0 : key0;
+        k.key1 = KU ? uniform.key1 : key1;
+        k.id0 = id0; k.id1 = id1;
+        return k;
+    }
+};
+
+// FP32 candidates need no regime and no p: the word split point and the
+// reciprocal part widths stand in for them.  Twelve words per request; with
+// a per-lane key the reciprocals give way to the key and are recomputed.
+template <>
+struct UparSlot<float, true> {
+    float X, a, u0, th0, inv_lo, inv_hi;
+    uint32_t wp, id0, id1, b0lo, b0hi;
+    uint32_t base;
+    __device__ __forceinline__ void put(const UparReq<float> &q, const RngKey &k)
+    {
+        X = q.X; a = q.a; u0 = q.u0; th0 = q.th0; inv_lo = q.inv_lo; inv_hi = q.inv_hi;
+        wp = q.wp; id0 = k.id0; id1 = k.id1;
+    }
+    __device__ __forceinline__ UparReq<float> req() const
+    {
+        UparReq<float> q;
+        q.X = X; q.a = a; q.u0 = u0; q.p = 0.0f; q.th0 = th0; q.regime = UPAR_SPLIT;
+        q.wp = wp; q.inv_lo = inv_lo; q.inv_hi = inv_hi;
+        return q;
+    }
+    __device__ __forceinline__ RngKey key(const RngKey &uniform) const
+    {
+        RngKey k;
+        k.key0 = uniform.key0; k.key1 = uniform.key1; k.id0 = id0; k.id1 = id1;
+        return k;
+    }
+};
+
+template <>
+struct UparSlot<float, false> {
+    float X, a, u0, th0;
+    uint32_t wp, key0, key1, id0, id1, b0lo, b0hi;
+    uint32_t base;
+    __device__ __forceinline__ void put(const UparReq<float> &q, const RngKey &k)
+    {
+        X = q.X; a = q.a; u0 = q.u0; th0 = q.th0; wp = q.wp;
+        key0 = k.key0; key1 = k.key1; id0 = k.id0; id1 = k.id1;
+    }
+    __device__ __forceinline__ UparReq<float> req() const
+    {
+        UparReq<float> q;
+        q.X = X; q.a = a; q.u0 = u0; q.p = 0.0f; q.th0 = th0; q.regime = UPAR_SPLIT;
+        q.wp = wp;
+        q.inv_lo = __builtin_amdgcn_rcpf((float)wp);
+        q.inv_hi = __builtin_amdgcn_rcpf((float)(0u - wp));
+        return q;
+    }
+    __device__ __forceinline__ RngKey key(const RngKey &) const
+    {
+        RngKey k;
+        k.key0 = key0; k.key1 = key1; k.id0 = id0; k.id1 = id1;
+        return k;
+    }
 };
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -834,7 +914,7 @@ __device__ __forceinline__ uint32_t small_div(uint32_t n, float inv_m)
 template <typename R, bool KEY_UNIFORM>
 __device__ __forceinline__ uint32_t coop_upar(bool need, const UparReq<R> &q, const RngKey &key,
                                               uint64_t B0, R &u, uint32_t &t, bool &ok,
-                                              UparSlot<R> *slots, int32_t *table,
+                                              UparSlot<R, KEY_UNIFORM> *slots, int32_t *table,
                                               uint32_t *first)
 {
     const int lane = threadIdx.x & 63;
@@ -842,9 +922,8 @@ __device__ __forceinline__ uint32_t coop_upar(bool need, const UparReq<R> &q, co
     uint32_t base = 0;
     uint32_t rounds = 0;
     if (need) {
-        UparSlot<R> s;
-        s.X = q.X; s.a = q.a; s.u0 = q.u0; s.p = q.p; s.th0 = q.th0; s.regime = q.regime;
-        s.key0 = key.key0; s.key1 = key.key1; s.id0 = key.id0; s.id1 = key.id1;
+        UparSlot<R, KEY_UNIFORM> s;
+        s.put(q, key);
         s.b0lo = (uint32_t)B0; s.b0hi = (uint32_t)(B0 >> 32);
         s.base = 0;
         slots[lane] = s;
@@ -863,13 +942,9 @@ __device__ __forceinline__ uint32_t coop_upar(bool need, const UparReq<R> &q, co
         wave_lds_sync();
         const uint32_t ss = small_div((uint32_t)lane, inv_m);
         const int rr = lane - (int)ss * m;
-        const UparSlot<R> s = slots[table[rr]];
-        UparReq<R> qq;
-        qq.X = s.X; qq.a = s.a; qq.u0 = s.u0; qq.p = s.p; qq.th0 = s.th0; qq.regime = s.regime;
-        RngKey kk;
-        kk.key0 = KEY_UNIFORM ? key.key0 : s.key0;
-        kk.key1 = KEY_UNIFORM ? key.key1 : s.key1;
-        kk.id0 = s.id0; kk.id1 = s.id1;
+        const UparSlot<R, KEY_UNIFORM> s = slots[table[rr]];
+        const UparReq<R> qq = s.req();
+        const RngKey kk = s.key(key);
         const uint64_t b0 = ((uint64_t)s.b0hi << 32) | s.b0lo;
         R uc;
         uint32_t half = 0;
@@ -943,7 +1018,7 @@ constexpr int transport_min_blocks()
 template <typename R, bool CAMS, bool SINGLE>
 __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_transport(LaunchView L, JobView J1)
 {
-    __shared__ UparSlot<R> s_slots[4][64];
+    __shared__ UparSlot<R, SINGLE> s_slots[4][64];
     __shared__ int32_t s_table[4][64];
     __shared__ uint32_t s_first[4][64];
     __shared__ unsigned long long s_counts[kLaneCounters][kMaxBlock];
@@ -1247,7 +1322,7 @@ __global__ __launch_bounds__(256) void k_sample(int what, double p0, double p1, 
                                                 uint64_t seed, int64_t n, double *out,
                                                 int32_t *draws)
 {
-    __shared__ UparSlot<R> s_slots[4][64];
+    __shared__ UparSlot<R, false> s_slots[4][64];
     __shared__ int32_t s_table[4][64];
     __shared__ uint32_t s_first[4][64];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
