@@ -266,7 +266,11 @@ colt_status colt_eval_voigt(int32_t precision, const double *a, const double *x,
  *   what 3: uniform numbers (k = 0 .. p0-1 of stream i) out[n*p0]
  *   what 4: as 0 with x_i = p1 + 0.41 (i mod 23) (-1)^i (mixed requests in a wave)
  *   what 5: as 0 with the one-lane sequential sampler
- *   what 6: as 4 with the one-lane sequential sampler */
+ *   what 6: as 4 with the one-lane sequential sampler
+ *   what 7: after p0 single draws (0..4096), the five draws of a scattering
+ *           (u_perp pair, mu, phi, next tau) as transport takes them: in FP32
+ *           from a block boundary its two generator blocks are computed
+ *           together; equal to draws p0 .. p0+4 of what 3  out[5n] */
 colt_status colt_sample(int32_t what, int32_t precision, double p0, double p1, double p2,
                         uint64_t seed, int64_t n, double *out, int32_t *draws, void *stream);
 

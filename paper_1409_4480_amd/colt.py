@@ -393,10 +393,10 @@ def eval_voigt(a, x, precision=FP64):
 
 def sample(what, n, seed, p0=0.0, p1=0.0, p2=0.0, precision=FP64):
     """Device sampler draws (see colt_sample): 'upar', 'uperp', 'mu', 'uniform',
-    'upar_mixed', 'upar_seq', 'upar_mixed_seq'."""
+    'upar_mixed', 'upar_seq', 'upar_mixed_seq', 'scatter_draws'."""
     code = {"upar": 0, "uperp": 1, "mu": 2, "uniform": 3, "upar_mixed": 4, "upar_seq": 5,
-            "upar_mixed_seq": 6}[what]
-    per = 2 if code == 1 else (int(p0) if code == 3 else 1)
+            "upar_mixed_seq": 6, "scatter_draws": 7}[what]
+    per = {1: 2, 3: int(p0), 7: 5}.get(code, 1)
     out = np.zeros(n * per)
     draws = np.zeros(n, np.int32)
     _check(lib().colt_sample(code, int(precision), float(p0), float(p1), float(p2), int(seed),

@@ -898,12 +898,13 @@ colt_status colt_sample(int32_t what, int32_t precision, double p0, double p1, d
                         uint64_t seed, int64_t n, double *out, int32_t *draws, void *stream)
 {
     const bool upar = what == 0 || what == 4 || what == 5 || what == 6;
-    if (what < 0 || what > 6 || n < 0 || (n > 0 && !out) || (upar && n > 0 && !draws))
+    if (what < 0 || what > 7 || n < 0 || (n > 0 && !out) || (upar && n > 0 && !draws))
         return fail(COLT_ERR_ARG, "bad sampler request");
     if (precision != 0 && precision != 1) return fail(COLT_ERR_ARG, "precision 0 or 1");
     if (what == 3 && !(p0 >= 1.0 && p0 <= 4096.0)) return fail(COLT_ERR_ARG, "1..4096 draws");
+    if (what == 7 && !(p0 >= 0.0 && p0 <= 4096.0)) return fail(COLT_ERR_ARG, "0..4096 skipped");
     if (n == 0) return COLT_OK;
-    const int64_t per = (what == 1) ? 2 : ((what == 3) ? (int64_t)p0 : 1);
+    const int64_t per = (what == 1) ? 2 : ((what == 3) ? (int64_t)p0 : ((what == 7) ? 5 : 1));
     hipStream_t s = (hipStream_t)stream;
     double *d = nullptr;
     int32_t *dd = nullptr;

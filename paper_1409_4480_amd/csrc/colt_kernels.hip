@@ -1365,6 +1365,18 @@ __global__ __launch_bounds__(256) void k_sample(int what, double p0, double p1, 
         uint32_t tries = 0;
         out[i] = (double)draw_upar<R>((R)p0, x, (R)p2, rng, tries);
         draws[i] = (int32_t)rng.k;
+    } else if (what == 7) {
+        const int64_t skip = (int64_t)p0;
+        for (int64_t j = 0; j < skip; ++j) (void)rng.next();
+        R d[5];
+        if constexpr (sizeof(R) == 4) {
+            rng.next5(d);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) d[j] = rng.next();
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) out[5 * i + j] = (double)d[j];
     } else {
         const int64_t m = (int64_t)p0;
         for (int64_t j = 0; j < m; ++j) out[i * m + j] = (double)rng.next();

@@ -97,6 +97,10 @@ def test_invalid_samplers_and_launches_are_rejected():
     out = np.zeros(4)
     dp = ctypes.POINTER(ctypes.c_double)
     assert L.colt_sample(9, 0, 0, 0, 0, 1, 4, out.ctypes.data_as(dp), None, None) == -1
+    assert L.colt_sample(8, 0, 0, 0, 0, 1, 4, out.ctypes.data_as(dp), None, None) == -1
+    # scattering draws: 0..4096 leading draws
+    assert L.colt_sample(7, 1, -1.0, 0, 0, 1, 4, out.ctypes.data_as(dp), None, None) == -1
+    assert L.colt_sample(7, 1, 5000.0, 0, 0, 1, 4, out.ctypes.data_as(dp), None, None) == -1
     assert L.colt_sample(2, 5, 0, 0, 0, 1, 4, out.ctypes.data_as(dp), None, None) == -1
     assert L.colt_eval_voigt(3, None, None, 4, None, None) == -1
     lc = colt.Launch(100, 0, 0, 0)                        # block not a multiple of 64

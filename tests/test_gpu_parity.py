@@ -95,6 +95,19 @@ def test_device_uniforms_are_the_oracle_stream():
             assert u32[i, k] == float(exp)
 
 
+@pytest.mark.parametrize("prec", [colt.FP64, colt.FP32_BULK])
+def test_scattering_draws_are_the_stream(prec):
+    """The five draws of a scattering, which FP32 takes from two generator
+    blocks computed together when they start on a block boundary (skip a
+    multiple of 4) and one by one otherwise, are draws skip .. skip+4 of the
+    photon's stream."""
+    n = 200
+    for skip in (0, 4, 8, 1, 2, 3, 6):
+        d = colt.sample("scatter_draws", n, seed=0x5EED + skip, p0=skip, precision=prec)
+        u = colt.sample("uniform", n, seed=0x5EED + skip, p0=skip + 5, precision=prec)
+        assert np.array_equal(d, u[:, skip:skip + 5]), skip
+
+
 def test_device_voigt_matches_oracle():
     a = np.concatenate([np.full(4000, 4.702e-4), np.full(2000, 0.047)])
     x = np.concatenate([np.linspace(-30, 30, 4000), np.linspace(0, 8, 2000)])
