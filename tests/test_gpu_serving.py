@@ -63,12 +63,13 @@ def test_autotuner_picks_and_caches_a_launch_shape(tmp_path):
     from paper_1409_4480_amd import autotune
     wl = inputs.dusty_sphere(n=16, tau0=1e5, n_photons=1)
     cache = str(tmp_path / "tune.json")
-    space = [(256, 1), (128, 2), (64, 4)]
+    space = [(256, 1), (128, 2), (64, 4), (256, 2, 4)]
     r = autotune.tune(wl, space=space, photons=20_000, cache_path=cache)
-    assert not r["cached"] and (r["block"], r["blocks_per_cu"]) in space
-    assert len(r["table"]) == 3 and all(e["scatterings_per_s"] > 0 for e in r["table"])
+    shapes = {(e[0], e[1], e[2] if len(e) > 2 else 0) for e in space}
+    assert not r["cached"] and (r["block"], r["blocks_per_cu"], r["march_min"]) in shapes
+    assert len(r["table"]) == 4 and all(e["scatterings_per_s"] > 0 for e in r["table"])
     r2 = autotune.tune(wl, space=space, photons=20_000, cache_path=cache)
-    assert r2["cached"] and r2["block"] == r["block"]
+    assert r2["cached"] and r2["block"] == r["block"] and r2["march_min"] == r["march_min"]
 
 
 def test_graph_replays_match_eager_transport():
