@@ -38,8 +38,8 @@ DRAWS_PER = {"upar_tries": 3, "scat_hi": 5, "scat_dust": 4, "emitted": 3}
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration
 # (profiles/k_transport_fp32_dusty_sphere_64.md).  They hold for the kernel
 # sources they were taken on; for any other sources traffic is reported null.
-TRAFFIC = {"sources_sha256": "374b871f1da244aadd2eed08c8f278504d7844afaa3b7a7940547392a810c831",
-           "fetch_bytes": 37130306, "write_bytes": 24065216}
+TRAFFIC = {"sources_sha256": "b65fed1d335a81208c48bad7e99f294087d13824f4f9b36c208bd63cace97338",
+           "fetch_bytes": 37196103, "write_bytes": 24059648}
 KERNEL_SOURCES = ["colt_kernels.hip", "colt_device.h", "colt_internal.h"]
 
 
