@@ -178,7 +178,7 @@ def precision_errors(grid, wl):
     return res
 
 
-def workloads_section(n_photons=262144, cap=2000):
+def workloads_section(n_photons=262144, cap=2000, only=None):
     """Throughput of the other workloads, a full photon pool each, FP32-bulk:
     the 128^3 first-galaxy halo (8 cameras, 256^2 images, 1000 bins), the ~2e6-
     leaf NFW octree (4 cameras, 512^2 images, non-local core-skipping estimate
@@ -197,6 +197,10 @@ def workloads_section(n_photons=262144, cap=2000):
               lambda: galaxy.Model("WL7").workload(n_photons=n_photons, npix=128, base_level=4,
                                                    max_extra=5, factors=(16, 8, 16, 128)), cap),
              ("slab_tau1e7", lambda: inputs.slab(tau0=1.0e7, n_photons=n_photons), 0)]
+    if only:
+        cases = [c for c in cases if c[0] == only]
+        if not cases:
+            raise SystemExit(f"no workload named {only!r}")
     out = {}
     for name, make, ev_cap in cases:
         wl = make()
@@ -244,6 +248,9 @@ def main():
                     help="skip the other workloads (cameras, octrees, galaxy model, slab)")
     ap.add_argument("--serve-jobs", type=int, default=48,
                     help="jobs in the serving stream (0 skips the serving section)")
+    ap.add_argument("--only-workload", default=None,
+                    help="only run this entry of the workloads section (e.g. halo_128cube_8cams) "
+                         "and print its figures")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -267,6 +274,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+        return
+    if args.only_workload:
+        print(json.dumps(workloads_section(only=args.only_workload)))
         return
     stream = torch.cuda.current_stream()
     wl = workload(args.photons, 1409448002)
