@@ -51,6 +51,45 @@ def test_512_jobs_in_one_launch_equal_each_job_alone():
                for f, w in zip(fused, wls))
 
 
+@pytest.mark.parametrize("case", ["dusty", "halo"])
+def test_fp32_job_alone_equals_the_job_in_a_fused_launch(case):
+    """FP32-bulk: a one-job launch (its job passed to the kernel by value) and
+    a launch that fuses the job with another (the job table read per lane) give
+    every photon the same history: equal escape frequency, scattering count and
+    fate, the recorded position and camera sums equal up to the last bits of
+    their final rounding."""
+    if case == "dusty":
+        wl = inputs.dusty_sphere(n=16, tau0=1e5, n_photons=5000, seed=3)
+        cap = 0
+    else:
+        wl = inputs.halo(n=32, n_photons=2000, seed=4)
+        cap = 3000
+        wl["params"]["max_events"] = cap
+    other = inputs.static_sphere(n=8, tau0=1e4, n_photons=3000, seed=9)
+    say(f"[gpu] FP32 {case}: alone and fused with a second job")
+    alone = colt.run(wl, precision=colt.FP32_BULK, record=True, max_events=cap)
+    g1, g2 = colt.Grid(wl["grid"]), colt.Grid(other["grid"])
+    j1 = colt.Job(g1, wl["source"], wl["params"], precision=colt.FP32_BULK, record=True,
+                  max_events=cap)
+    j2 = colt.Job(g2, other["source"], other["params"], precision=colt.FP32_BULK)
+    try:
+        colt.transport([j1, j2])
+        fused = j1.tally()
+    finally:
+        j1.release()
+        j2.release()
+        g1.release()
+        g2.release()
+    a, f = alone["records"], fused["records"]
+    for key in ("x", "nscat", "status"):
+        assert np.array_equal(a[key], f[key]), key
+    box = float(np.max(np.asarray(wl["grid"]["box_max"]) - np.asarray(wl["grid"]["box_min"])))
+    assert np.abs(a["pos"] - f["pos"]).max() <= 1e-12 * box
+    if case == "halo":
+        assert np.allclose(a["peel"], f["peel"], rtol=1e-12, atol=1e-300)
+        assert a["peel"].sum() > 0
+
+
 def test_64_cameras_match_the_oracle():
     """A job with the largest camera count: 64 directions on a spiral."""
     m = 64
