@@ -101,3 +101,29 @@ def test_graph_replays_match_eager_transport():
     graph.release()
     for h in (j1, j2, g1, g2):
         h.release()
+
+
+def test_graph_of_one_fp32_job_matches_eager_transport():
+    """A one-job FP32 graph (the job passed to the kernel by value at capture)
+    replayed three times equals one eager launch of the whole job."""
+    import torch
+    wl = inputs.dusty_sphere(n=8, tau0=1e5, n_photons=900, seed=21)
+    ref = colt.run(wl, precision=colt.FP32_BULK, record=True)
+    g = colt.Grid(wl["grid"])
+    j = colt.Job(g, wl["source"], wl["params"], precision=colt.FP32_BULK, record=True)
+    graph = colt.Graph([j], photons_per_job=300)
+    try:
+        for rep in range(3):
+            say(f"[gpu] one-job FP32 graph replay {rep}")
+            graph.launch()
+            torch.cuda.synchronize()
+            assert j.status()[0] == 300 * (rep + 1)
+        out = j.tally()
+        for k in ("x", "nscat", "status", "pos"):
+            assert np.array_equal(out["records"][k], ref["records"][k]), k
+        assert np.array_equal(out["spectrum"], ref["spectrum"])
+        assert out["counters"]["scat_hi"] == ref["counters"]["scat_hi"]
+    finally:
+        graph.release()
+        j.release()
+        g.release()
