@@ -55,7 +55,7 @@ class _Out(ctypes.Structure):
     _fields_ = [("spectrum", _dp), ("cam_spec", _dp), ("cam_img", _dp),
                 ("counters", ctypes.c_uint64 * N_COUNTERS), ("rec_x", _dp),
                 ("rec_nscat", _ip), ("rec_status", _ip), ("rec_pos", _dp),
-                ("rec_peel", _dp)]
+                ("rec_peel", _dp), ("rec_len", _dp)]
 
 
 _lib = None
@@ -225,7 +225,7 @@ def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=No
     Returns a dict with the escape spectrum (under/overflow at both ends), the
     camera spectra and images (raw sums of W exp(-tau)), the event counters
     and, if ``records``, per-photon final lab x, scattering count, status,
-    position and summed peel-off weight per camera.
+    position, summed peel-off weight per camera and path length travelled (cm).
     """
     n_ph = int(params["n_photons"])
     if id_end is None:
@@ -285,12 +285,13 @@ def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=No
     if records:
         rec = {"x": np.zeros(n_run), "nscat": np.zeros(n_run, np.int32),
                "status": np.zeros(n_run, np.int32), "pos": np.zeros((n_run, 3)),
-               "peel": np.zeros((n_run, max(n_cams, 1)))}
+               "peel": np.zeros((n_run, max(n_cams, 1))), "len": np.zeros(n_run)}
         o.rec_x = _ptr(rec["x"])
         o.rec_nscat = _ptr(rec["nscat"], _ip)
         o.rec_status = _ptr(rec["status"], _ip)
         o.rec_pos = _ptr(rec["pos"])
         o.rec_peel = _ptr(rec["peel"]) if n_cams else None
+        o.rec_len = _ptr(rec["len"])
     rc = lib().orc_run(ctypes.byref(g), ctypes.byref(s), ctypes.byref(p), ctypes.byref(o),
                        int(threads))
     if rc != 0:

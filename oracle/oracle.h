@@ -92,6 +92,7 @@ typedef struct {
     int32_t *rec_status;       /* 1 escaped, 2 absorbed, 3 stopped by max_events      */
     double *rec_pos;           /* 3 per photon, final position (cm)                   */
     double *rec_peel;          /* n_cams per photon, summed W exp(-tau)               */
+    double *rec_len;           /* path length travelled from emission to the end (cm) */
 } orc_out;
 
 /* Runs photons [id_begin, id_end) with n_threads worker threads; returns 0 or <0. */

@@ -242,6 +242,37 @@ def test_dust_only_sphere_escape_is_exp_minus_tau(threads, tau_d):
     assert out["counters"]["escaped"] == n
 
 
+@pytest.mark.parametrize("tau_d", [0.1, 0.3])
+def test_dust_with_hi_is_attenuation_along_the_walk(threads, tau_d):
+    """Grey absorbing dust (albedo 0) in resonantly scattering gas: absorption
+    and H I scattering are competing Poisson processes along the path, so a
+    photon survives its whole walk with probability exp(-k_d L), L the length
+    of that walk without dust.  The escape fraction with dust must equal the
+    mean of exp(-k_d L) over dust-free histories of the same gas; this pins the
+    channel choice (k_d / k_tot), the absorption and that dust leaves the H I
+    walk itself untouched.  The two runs draw independent histories."""
+    n = 6000
+    k_d = tau_d / PC
+    clean = inputs.static_sphere(n=8, tau0=1e3, n_photons=n, seed=61, isotropic=False)
+    out = oracle.run(clean["grid"], clean["source"], clean["params"], records=True,
+                     threads=threads)
+    L = out["records"]["len"]
+    assert np.all(L >= PC * (1 - 1e-9))           # at least the radius to the edge
+    surv = np.exp(-k_d * L)
+    pred, se_pred = surv.mean(), surv.std() / math.sqrt(n)
+    dusty = inputs.static_sphere(n=8, tau0=1e3, n_photons=n, seed=62, isotropic=False,
+                                 k_dust=k_d, albedo=0.0)
+    c = oracle.run(dusty["grid"], dusty["source"], dusty["params"], threads=threads)["counters"]
+    f = c["escaped"] / n
+    se = math.sqrt(f * (1 - f) / n + se_pred ** 2)
+    assert 0.05 < f < 0.95
+    assert abs(f - pred) < 4.0 * se, (f, pred, se)
+    # albedo 1: the dust interactions all scatter and nothing is lost
+    dusty["grid"]["albedo"] = 1.0
+    c = oracle.run(dusty["grid"], dusty["source"], dusty["params"], threads=threads)["counters"]
+    assert c["escaped"] == n and c["absorbed"] == 0 and c["scat_dust"] > 0
+
+
 def test_dusty_sphere_conservation(threads):
     w = inputs.dusty_sphere(n=8, tau0=1e5, n_photons=1000, seed=41)
     out = oracle.run(w["grid"], w["source"], w["params"], records=True, threads=threads)
