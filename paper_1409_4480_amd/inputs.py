@@ -188,7 +188,7 @@ def gaussian_random_field(n, slope=-11.0 / 3.0, rms=1.0, seed=0):
     k = np.sqrt(kx * kx + ky * ky + kz * kz)
     k[0, 0, 0] = np.inf
     fk *= k ** (slope / 2.0)
-    f = np.fft.irfftn(fk, s=(n, n, n))
+    f = np.fft.irfftn(fk, s=(n, n, n), axes=(0, 1, 2))
     f -= f.mean()
     f *= rms / f.std()
     return f

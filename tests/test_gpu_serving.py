@@ -33,6 +33,27 @@ def test_each_job_same_alone_and_in_the_mix():
             assert alone["counters"][k] == m["counters"][k]
 
 
+def test_admission_footprint_bounds_the_device_bytes():
+    """The server admits by an estimate made before anything is allocated; it
+    must not undercount what the library then holds for the grid and the job
+    (records on, with and without cameras, Cartesian and octree)."""
+    cases = small_stream(n=4, seed=6)
+    cases.append(inputs.halo(n=32, n_photons=500, seed=7))
+    cases.append(inputs.nfw_octree(base_level=3, max_extra=2, leaves_target=(500, 4000),
+                                   turb_n=32, n_photons=300, seed=8, npix=64))
+    for wl in cases:
+        g = colt.Grid(wl["grid"])
+        j = colt.Job(g, wl["source"], wl["params"], precision=colt.FP32_BULK, record=True)
+        try:
+            held = g.nbytes + j.nbytes
+            est = serving.footprint(wl, record=True)
+            say(f"    {wl.get('name', '?')}: estimate {est} B, held {held} B")
+            assert est >= held, (wl.get("name"), est, held)
+        finally:
+            j.release()
+            g.release()
+
+
 def test_memory_budget_queues_jobs_without_changing_results():
     jobs = small_stream(n=5, seed=4)
     biggest = max(serving.footprint(wl, record=True) for wl in jobs)
