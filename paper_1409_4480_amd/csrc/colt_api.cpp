@@ -11,6 +11,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "colt.h"
@@ -42,6 +43,73 @@ colt_status fail(colt_status code, const char *fmt, ...)
         if (e_ != hipSuccess)                                                         \
             return fail(COLT_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
+
+// Octree neighbour links: for every leaf and face (2 axis + (step > 0)), the
+// node across that face at the leaf's own level, or the coarser leaf that
+// covers it there.  An entry holds the node and how many levels coarser it is,
+// (up << 27) | node; kRopeEdge marks the domain face and kRopeSearch a case the
+// encoding cannot hold (the transport then searches from the root).  Built
+// with exact integer coordinates in units of the finest cell.
+constexpr uint32_t kRopeEdge = 0xFFFFFFFFu, kRopeSearch = 0xFFFFFFFEu;
+
+void build_ropes(const int32_t *child, int64_t nn, const std::vector<int32_t> &depth,
+                 const std::vector<int64_t> &order, const std::vector<int64_t> &leaf_src,
+                 std::vector<uint32_t> &rope)
+{
+    int dmax = 0;
+    for (int64_t i = 0; i < nn; ++i) dmax = std::max(dmax, depth[i]);
+    std::vector<int64_t> lo((size_t)nn * 3, 0);
+    for (int64_t i : order) {                 // parents before children
+        const int32_t c = child[i];
+        if (c < 0) continue;
+        const int64_t half = int64_t(1) << (dmax - depth[i] - 1);
+        for (int o = 0; o < 8; ++o)
+            for (int d = 0; d < 3; ++d)
+                lo[(size_t)(c + o) * 3 + d] = lo[(size_t)i * 3 + d] + (((o >> d) & 1) ? half : 0);
+    }
+    const int64_t extent = int64_t(1) << dmax;
+    const int64_t nl = (int64_t)leaf_src.size();
+    rope.assign((size_t)nl * 6, kRopeSearch);
+    auto work = [&](int64_t j0, int64_t j1) {
+        for (int64_t j = j0; j < j1; ++j) {
+            const int64_t leaf = leaf_src[j];
+            const int dl = depth[leaf];
+            const int64_t size = int64_t(1) << (dmax - dl);
+            for (int face = 0; face < 6; ++face) {
+                const int a = face >> 1;
+                int64_t q[3] = {lo[leaf * 3], lo[leaf * 3 + 1], lo[leaf * 3 + 2]};
+                q[a] = (face & 1) ? q[a] + size : q[a] - 1;      // first unit across
+                if (q[a] < 0 || q[a] >= extent) {
+                    rope[(size_t)j * 6 + face] = kRopeEdge;
+                    continue;
+                }
+                int64_t node = 0;
+                int lvl = 0;
+                int64_t nlo[3] = {0, 0, 0};
+                while (child[node] >= 0 && lvl < dl) {
+                    const int64_t half = int64_t(1) << (dmax - lvl - 1);
+                    int oct = 0;
+                    for (int d = 0; d < 3; ++d)
+                        if (q[d] - nlo[d] >= half) { oct |= 1 << d; nlo[d] += half; }
+                    node = child[node] + oct;
+                    ++lvl;
+                }
+                const int up = dl - lvl;
+                if (node < (int64_t(1) << 27) && up < 32)
+                    rope[(size_t)j * 6 + face] = ((uint32_t)up << 27) | (uint32_t)node;
+            }
+        }
+    };
+    const int64_t nt = std::max<int64_t>(1, std::min<int64_t>(16, std::thread::hardware_concurrency()));
+    if (nl < 4096 || nt == 1) {
+        work(0, nl);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int64_t t = 0; t < nt; ++t)
+        th.emplace_back(work, nl * t / nt, nl * (t + 1) / nt);
+    for (auto &x : th) x.join();
+}
 
 // Device memory from the caller's allocator (or hipMalloc), remembered for release.
 struct DevMem {
@@ -192,6 +260,7 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
     // leaf list (index into the caller's arrays) and device node table
     std::vector<int64_t> leaf_src;
     std::vector<int32_t> child_dev, base_dev;
+    std::vector<uint32_t> rope_dev;
     int nb = 0;
     if (d->kind == 0) {
         if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0)
@@ -257,6 +326,7 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
             }
         }
         g->n_leaves = (int64_t)leaf_src.size();
+        build_ropes(d->child, nn, depth, order, leaf_src, rope_dev);
         base_dev.resize((size_t)nb * nb * nb);
         for (int iz = 0; iz < nb; ++iz)
             for (int iy = 0; iy < nb; ++iy)
@@ -297,12 +367,14 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
     void *rf = g->mem.get((size_t)nl * sizeof(CellRec<float>));
     void *af = g->mem.get((size_t)nl * sizeof(CellAux<float>));
     g->n_dev = (double *)g->mem.get((size_t)nl * sizeof(double));
-    void *dchild = nullptr, *dbase = nullptr;
+    void *dchild = nullptr, *dbase = nullptr, *drope = nullptr;
     if (d->kind == 1) {
         dchild = g->mem.get(child_dev.size() * sizeof(int32_t));
         dbase = g->mem.get(base_dev.size() * sizeof(int32_t));
+        drope = g->mem.get(rope_dev.size() * sizeof(uint32_t));
     }
-    if (!stage || !rd || !ad || !rf || !af || !g->n_dev || (d->kind == 1 && (!dchild || !dbase))) {
+    if (!stage || !rd || !ad || !rf || !af || !g->n_dev ||
+        (d->kind == 1 && (!dchild || !dbase || !drope))) {
         g->mem.release_all();
         delete g;
         return fail(COLT_ERR_NOMEM, "device allocation for the grid failed");
@@ -315,6 +387,9 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
                            hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(dbase, base_dev.data(), base_dev.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(drope, rope_dev.data(), rope_dev.size() * sizeof(uint32_t),
                                hipMemcpyHostToDevice, s);
     }
     const double *sd = (const double *)stage;
@@ -340,6 +415,7 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
     v.aux = ad;
     v.child = (const int32_t *)dchild;
     v.base = (const int32_t *)dbase;
+    v.rope = (const uint32_t *)drope;
     for (int i = 0; i < 3; ++i) v.centre[i] = 0.5 * ext[i] / g->dx_cm;
     v.esc_r = d->escape_radius / g->dx_cm;
     v.albedo = d->dust_albedo;
@@ -677,7 +753,8 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
         const uint64_t total = prefix.back();
         int per_cu = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 0;
         if (per_cu <= 0) {
-            HIP_TRY(transport_occupancy(prec, cams, nj == 1, block, &per_cu));
+            HIP_TRY(transport_occupancy(prec, cams, nj == 1, nj == 1 ? views[0].g.kind : -1, block,
+                                        &per_cu));
             if (per_cu <= 0) per_cu = 1;
         }
         const uint64_t lanes_needed = (total + 63) / 64 * 64;
@@ -729,7 +806,8 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
     if (block < 64 || block > 256 || block % 64) return fail(COLT_ERR_ARG, "block 64..256");
     int per_cu = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 0;
     if (per_cu <= 0) {
-        HIP_TRY(transport_occupancy(prec, cams, n_jobs == 1, block, &per_cu));
+        HIP_TRY(transport_occupancy(prec, cams, n_jobs == 1,
+                                    n_jobs == 1 ? jobs[0]->view.g.kind : -1, block, &per_cu));
         if (per_cu <= 0) per_cu = 1;
     }
     const int nj = n_jobs;

@@ -39,6 +39,7 @@ struct GridView {
     const void *aux;           // CellAux<R>[n_cells]
     const int32_t *child;      // octree: >= 0 first child, < 0 -(leaf + 1)
     const int32_t *base;       // octree: node at the base level per base cell
+    const uint32_t *rope;      // octree: per leaf and face, the node across (see cross())
     double centre[3];          // box centre
     double esc_r;              // escape sphere radius (0 = box faces)
     double albedo;             // dust scattering probability per dust event

@@ -195,6 +195,61 @@ __device__ __forceinline__ void snap_face(CellBox &c, double r[3], const double 
     }
 }
 
+// Octree crossing through the leaf's neighbour link: the node across the face
+// (same level, or the coarser leaf there), then a descent inside it only if it
+// is refined.  Where r lies on one of that node's other faces and k points out
+// of it, the tie rules of the search from the root could pick a diagonal
+// cell, so that case, and links the set-up could not encode, use the search.
+// Either way the cell is the one locate() finds.
+__device__ __forceinline__ bool cross_octree(const GridView &g, CellBox &c, const double r[3],
+                                             const double k[3], int axis, int step)
+{
+    const uint32_t e = g.rope[(size_t)c.cell * 6 + 2 * axis + (step > 0 ? 1 : 0)];
+    if (e == 0xFFFFFFFFu) return false;                  // the domain face
+    if (e == 0xFFFFFFFEu) return locate(g, r, k, c);
+    const int up = (int)(e >> 27);
+    int node = (int)(e & 0x7FFFFFFu);
+    const double size = c.size * (double)(1u << up);     // exact (powers of two)
+    double lo[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double x = (d == axis) ? ((step > 0) ? c.lo[d] + c.size : c.lo[d] - c.size)
+                                     : c.lo[d];
+        lo[d] = (up == 0) ? x : ::floor(x / size) * size;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (d == axis) continue;
+        if ((r[d] == lo[d] && k[d] < 0.0) || (r[d] == lo[d] + size && !(k[d] < 0.0)))
+            return locate(g, r, k, c);
+    }
+    if (g.esc_r > 0.0) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) d2 += (r[d] - g.centre[d]) * (r[d] - g.centre[d]);
+        if (d2 >= g.esc_r * g.esc_r) return false;
+    }
+    c.lo[0] = lo[0]; c.lo[1] = lo[1]; c.lo[2] = lo[2];
+    double sz = size;
+    int ch = g.child[node];
+    while (ch >= 0) {
+        const double half = 0.5 * sz;
+        int oct = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int b = side_of(r[d], c.lo[d] + half, k[d]);
+            if (b) c.lo[d] += half;
+            oct |= b << d;
+        }
+        node = ch + oct;
+        sz = half;
+        ch = g.child[node];
+    }
+    c.size = sz;
+    c.cell = -ch - 1;
+    return true;
+}
+
 __device__ __forceinline__ bool cross(const GridView &g, CellBox &c, double r[3],
                                       const double k[3], int axis)
 {
@@ -215,6 +270,7 @@ __device__ __forceinline__ bool cross(const GridView &g, CellBox &c, double r[3]
         }
         return inside;
     }
+    if (g.rope) return cross_octree(g, c, r, k, axis, step);
     return locate(g, r, k, c);
 }
 
@@ -1012,10 +1068,11 @@ __device__ __forceinline__ int find_job(const LaunchView &L, uint64_t g)
 template <typename R, bool CAMS>
 constexpr int transport_min_blocks()
 {
-    return CAMS ? 1 : ((sizeof(R) == 4) ? COLT_FP32_MIN_BLOCKS : COLT_FP64_MIN_BLOCKS);
+    return CAMS ? ((sizeof(R) == 4) ? 2 : 1)
+                : ((sizeof(R) == 4) ? COLT_FP32_MIN_BLOCKS : COLT_FP64_MIN_BLOCKS);
 }
 
-template <typename R, bool CAMS, bool SINGLE>
+template <typename R, bool CAMS, bool SINGLE, int GK>
 __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_transport(LaunchView L, JobView J1)
 {
     __shared__ UparSlot<R, SINGLE> s_slots[4][64];
@@ -1050,7 +1107,16 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
     lc.col = &s_counts[0][threadIdx.x];
 #pragma unroll
     for (int i = 0; i < kLaneCounters; ++i) s_counts[i][threadIdx.x] = 0ull;
-    const JobView *const J_single = (sizeof(R) == 4) ? &J1 : L.jobs;
+    // GK fixes the grid kind of a one-job FP32 launch at compile time, so a
+    // Cartesian launch carries no octree code (0 Cartesian, 1 octree, -1 any)
+    JobView Jk = J1;
+    if constexpr (GK == 0) {
+        Jk.g.kind = 0;
+        Jk.g.rope = nullptr;
+    } else if constexpr (GK == 1) {
+        Jk.g.kind = 1;
+    }
+    const JobView *const J_single = (sizeof(R) == 4) ? &Jk : L.jobs;
     const JobView *J = SINGLE ? J_single : nullptr;
     const uint64_t total = L.prefix[L.n_jobs];
     const int march_min = L.march_min;
@@ -1399,19 +1465,19 @@ hipError_t launch_cell_setup(int64_t n, const double *n_HI, const double *T, con
     return hipGetLastError();
 }
 
-template <typename R, bool CAMS, bool SINGLE>
+template <typename R, bool CAMS, bool SINGLE, int GK = -1>
 static hipError_t launch_t(const LaunchView &L, const JobView &J1, int grid, int block,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL((k_transport<R, CAMS, SINGLE>), dim3(grid), dim3(block), 0, s, L, J1);
+    hipLaunchKernelGGL((k_transport<R, CAMS, SINGLE, GK>), dim3(grid), dim3(block), 0, s, L, J1);
     return hipGetLastError();
 }
 
-template <typename R, bool CAMS, bool SINGLE>
+template <typename R, bool CAMS, bool SINGLE, int GK = -1>
 static hipError_t occupancy_t(int block, int *blocks_per_cu)
 {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
-                                                        k_transport<R, CAMS, SINGLE>, block, 0);
+                                                        k_transport<R, CAMS, SINGLE, GK>, block, 0);
 }
 
 hipError_t launch_transport(int precision, bool cams, const LaunchView &L, const JobView &J1,
@@ -1424,13 +1490,17 @@ hipError_t launch_transport(int precision, bool cams, const LaunchView &L, const
         return single ? launch_t<double, false, true>(L, J1, grid, block, s)
                       : launch_t<double, false, false>(L, J1, grid, block, s);
     }
-    if (cams) return single ? launch_t<float, true, true>(L, J1, grid, block, s)
-                            : launch_t<float, true, false>(L, J1, grid, block, s);
-    return single ? launch_t<float, false, true>(L, J1, grid, block, s)
-                  : launch_t<float, false, false>(L, J1, grid, block, s);
+    if (!single)
+        return cams ? launch_t<float, true, false>(L, J1, grid, block, s)
+                    : launch_t<float, false, false>(L, J1, grid, block, s);
+    if (J1.g.kind == 0)
+        return cams ? launch_t<float, true, true, 0>(L, J1, grid, block, s)
+                    : launch_t<float, false, true, 0>(L, J1, grid, block, s);
+    return cams ? launch_t<float, true, true, 1>(L, J1, grid, block, s)
+                : launch_t<float, false, true, 1>(L, J1, grid, block, s);
 }
 
-hipError_t transport_occupancy(int precision, bool cams, bool single, int block,
+hipError_t transport_occupancy(int precision, bool cams, bool single, int grid_kind, int block,
                                int *blocks_per_cu)
 {
     if (precision == 0) {
@@ -1439,10 +1509,14 @@ hipError_t transport_occupancy(int precision, bool cams, bool single, int block,
         return single ? occupancy_t<double, false, true>(block, blocks_per_cu)
                       : occupancy_t<double, false, false>(block, blocks_per_cu);
     }
-    if (cams) return single ? occupancy_t<float, true, true>(block, blocks_per_cu)
-                            : occupancy_t<float, true, false>(block, blocks_per_cu);
-    return single ? occupancy_t<float, false, true>(block, blocks_per_cu)
-                  : occupancy_t<float, false, false>(block, blocks_per_cu);
+    if (!single)
+        return cams ? occupancy_t<float, true, false>(block, blocks_per_cu)
+                    : occupancy_t<float, false, false>(block, blocks_per_cu);
+    if (grid_kind == 0)
+        return cams ? occupancy_t<float, true, true, 0>(block, blocks_per_cu)
+                    : occupancy_t<float, false, true, 0>(block, blocks_per_cu);
+    return cams ? occupancy_t<float, true, true, 1>(block, blocks_per_cu)
+                : occupancy_t<float, false, true, 1>(block, blocks_per_cu);
 }
 
 hipError_t launch_plan(const PlanView &P, bool advance, hipStream_t s)

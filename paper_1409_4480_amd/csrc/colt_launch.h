@@ -14,7 +14,8 @@ hipError_t launch_cell_setup(int64_t n, const double *n_HI, const double *T, con
 // J1: the job of a one-job launch (L.n_jobs == 1), passed to the kernel by value
 hipError_t launch_transport(int precision, bool cams, const LaunchView &L, const JobView &J1,
                             int grid, int block, hipStream_t s);
-hipError_t transport_occupancy(int precision, bool cams, bool single, int block,
+// grid_kind: the grid kind of a one-job launch (0 Cartesian, 1 octree)
+hipError_t transport_occupancy(int precision, bool cams, bool single, int grid_kind, int block,
                                int *blocks_per_cu);
 hipError_t launch_plan(const PlanView &P, bool advance, hipStream_t s);
 hipError_t launch_nonlocal(const GridView &g, const double *n_HI, const double *leaf_boxes,

@@ -33,8 +33,8 @@ def footprint(wl, record=False):
     cams = p.get("cam_dir")
     n_cams = 0 if cams is None else np.asarray(cams).size // 3
     n += 8 * n_cams * (int(p.get("cam_nbins", 0)) + int(p.get("cam_npix", 0)) ** 2)
-    if g.get("child") is not None:
-        n += 4 * n_cells + 4 * 128 ** 3
+    if g.get("child") is not None:                     # child table, base table,
+        n += (4 + 24) * n_cells + 4 * 128 ** 3          # six neighbour links per leaf
     if record:
         n += 32 * int(p["n_photons"]) * (1 + n_cams)
     return n + (64 << 10)
