@@ -38,8 +38,8 @@ DRAWS_PER = {"upar_tries": 3, "scat_hi": 5, "scat_dust": 4, "emitted": 3}
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration
 # (profiles/k_transport_fp32_dusty_sphere_64.md).  They hold for the kernel
 # sources they were taken on; for any other sources traffic is reported null.
-TRAFFIC = {"sources_sha256": "b65fed1d335a81208c48bad7e99f294087d13824f4f9b36c208bd63cace97338",
-           "fetch_bytes": 37196103, "write_bytes": 24059648}
+TRAFFIC = {"sources_sha256": "c119bbd8e96942e2d65facb42e923d5adfa9ccef2760f0e02b4bae999963ee52",
+           "fetch_bytes": 35268615, "write_bytes": 23014752}
 KERNEL_SOURCES = ["colt_kernels.hip", "colt_device.h", "colt_internal.h"]
 
 
