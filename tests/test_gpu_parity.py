@@ -247,6 +247,23 @@ def test_octree_nfw_parity():
         assert abs(gp[:, i].mean() - rp[:, i].mean()) < 3 * se
 
 
+def test_octree_crossings_match_the_oracle_without_core_skipping():
+    """Octree with NFW gas, turbulence and 64 sources, no core-skipping (so no
+    position-dependent branch): FP64 histories, camera sums included, equal
+    the oracle's, whose octree crossings search from the root while the device
+    follows its per-leaf neighbour links."""
+    wl = inputs.nfw_octree(base_level=3, max_extra=3, leaves_target=(4000, 9000), turb_n=16,
+                           n_photons=400, npix=16, n_bins=100, tau0_max=3e3)
+    wl["params"]["xcrit_mode"] = 0
+    g, r = run_both(wl)
+    ok = compare_records(g, r, 4000 * PC, peel=True)
+    say(f"    crossings: device {g['counters']['crossings']}, oracle {r['counters']['crossings']}")
+    assert g["counters"]["crossings"] > 20 * 400
+    assert abs(g["counters"]["crossings"] - r["counters"]["crossings"]) <= \
+        FLIP * r["counters"]["crossings"]
+    assert ok.mean() >= 1.0 - FLIP
+
+
 def test_nonlocal_estimate_matches_oracle():
     """Device non-local a*tau (Sec. 3.2.4) against the oracle, Cartesian halo
     and NFW octree (per leaf)."""
