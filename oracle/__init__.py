@@ -95,6 +95,15 @@ def lib():
         L.orc_sample_mu.argtypes = [ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
         L.orc_upar_split.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
         L.orc_upar_split.restype = ctypes.c_double
+        L.orc_atau_jeans.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_atau_jeans.restype = ctypes.c_double
+        L.orc_xcrit_at.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), _dp, _dp,
+                                   ctypes.c_double]
+        L.orc_xcrit_at.restype = ctypes.c_double
+        L.orc_scatter_once.argtypes = [ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                       ctypes.c_uint64, _dp, _dp, _dp]
+        L.orc_scatter_once.restype = None
         _lib = L
     return _lib
 
@@ -165,6 +174,37 @@ def upar_split(a, x, xcw_val=None):
     return p, u0.value
 
 
+def atau_jeans(T, n_HI):
+    """a*tau of one Jeans length (Sec. 3.2.4, eq. atau0J)."""
+    return lib().orc_atau_jeans(float(T), float(n_HI))
+
+
+def xcrit_at(grid, params, r, k, x):
+    """x_crit of an H I scattering at r (cm) moving along k with comoving
+    frequency x, as the transport computes it; -1 outside the domain."""
+    keep = {}
+
+    def hold(name, arr):
+        keep[name] = arr
+        return arr
+    g = _grid_struct(grid, hold)
+    p = _params_struct(dict(params, n_photons=params.get("n_photons", 1)), 0, 1, hold)
+    rr = np.ascontiguousarray(r, dtype=np.float64)
+    kk = np.ascontiguousarray(k, dtype=np.float64)
+    return lib().orc_xcrit_at(ctypes.byref(g), ctypes.byref(p), _ptr(rr), _ptr(kk), float(x))
+
+
+def scatter_once(T, x, k_in, xcrit=0.0, recoil=True, isotropic=False, seed=1, photon=0):
+    """One H I scattering as the transport performs it; returns (x_f, k_f, u_par)."""
+    kk = np.ascontiguousarray(k_in, dtype=np.float64)
+    xf, up = ctypes.c_double(), ctypes.c_double()
+    kf = np.zeros(3)
+    lib().orc_scatter_once(float(T), float(x), _ptr(kk), float(xcrit), int(bool(recoil)),
+                           int(bool(isotropic)), int(seed), int(photon), ctypes.byref(xf),
+                           _ptr(kf), ctypes.byref(up))
+    return xf.value, kf, up.value
+
+
 def sample_uperp(xcrit_eff, n, seed):
     out = np.zeros((n, 2))
     lib().orc_sample_uperp(xcrit_eff, seed, n, _ptr(out))
@@ -219,6 +259,33 @@ def nonlocal_atau(grid, f_nl):
     return out
 
 
+def _params_struct(params, id_begin, id_end, hold):
+    p = _Params()
+    p.n_photons = int(params["n_photons"])
+    p.id_begin = id_begin
+    p.id_end = id_end
+    p.seed = int(params["seed"])
+    p.xcrit_mode = int(params.get("xcrit_mode", 0))
+    p.atau0 = float(params.get("atau0", 0.0))
+    p.recoil = int(params.get("recoil", 0))
+    p.isotropic = int(params.get("isotropic", 0))
+    p.n_bins = int(params.get("n_bins", 0))
+    p.x_min = float(params.get("x_min", -1.0))
+    p.x_max = float(params.get("x_max", 1.0))
+    cams = params.get("cam_dir")
+    n_cams = 0 if cams is None else int(np.asarray(cams).size // 3)
+    p.n_cams = n_cams
+    p.cam_dir = _ptr(hold("cams", _f64(cams).reshape(-1) if n_cams else None))
+    p.cam_nbins = int(params.get("cam_nbins", 0))
+    p.cam_xmin = float(params.get("cam_xmin", -1.0))
+    p.cam_xmax = float(params.get("cam_xmax", 1.0))
+    p.cam_npix = int(params.get("cam_npix", 0))
+    p.cam_fov = float(params.get("cam_fov", 1.0))
+    p.tau_peel_max = float(params.get("tau_peel_max", 50.0))
+    p.max_events = int(params.get("max_events", 0))
+    return p
+
+
 def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=None):
     """Runs photons [id_begin, id_end) of a job through the oracle.
 
@@ -250,29 +317,8 @@ def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=No
     s.sigma = float(source.get("sigma", 0.0))
     s.freq_mode = int(source.get("freq_mode", 0))
 
-    p = _Params()
-    p.n_photons = n_ph
-    p.id_begin = id_begin
-    p.id_end = id_end
-    p.seed = int(params["seed"])
-    p.xcrit_mode = int(params.get("xcrit_mode", 0))
-    p.atau0 = float(params.get("atau0", 0.0))
-    p.recoil = int(params.get("recoil", 0))
-    p.isotropic = int(params.get("isotropic", 0))
-    p.n_bins = int(params.get("n_bins", 0))
-    p.x_min = float(params.get("x_min", -1.0))
-    p.x_max = float(params.get("x_max", 1.0))
-    cams = params.get("cam_dir")
-    n_cams = 0 if cams is None else int(np.asarray(cams).size // 3)
-    p.n_cams = n_cams
-    p.cam_dir = _ptr(hold("cams", _f64(cams).reshape(-1) if n_cams else None))
-    p.cam_nbins = int(params.get("cam_nbins", 0))
-    p.cam_xmin = float(params.get("cam_xmin", -1.0))
-    p.cam_xmax = float(params.get("cam_xmax", 1.0))
-    p.cam_npix = int(params.get("cam_npix", 0))
-    p.cam_fov = float(params.get("cam_fov", 1.0))
-    p.tau_peel_max = float(params.get("tau_peel_max", 50.0))
-    p.max_events = int(params.get("max_events", 0))
+    p = _params_struct(params, id_begin, id_end, hold)
+    n_cams = int(p.n_cams)
 
     o = _Out()
     spectrum = np.zeros(p.n_bins + 2)

@@ -58,7 +58,8 @@ typedef struct {
     uint64_t n_photons;        /* photon ids 0 .. n_photons-1 form the job            */
     uint64_t id_begin, id_end; /* the oracle runs the id range [begin, end)           */
     uint64_t seed;
-    int32_t xcrit_mode;        /* 0 off, 1 global a*tau0, 2 local a*tau_cell + NL     */
+    int32_t xcrit_mode;        /* 0 off, 1 global a*tau0, 2 local a*tau_cell + NL,    */
+                               /* 3 Jeans a*tau_J of the cell (eq. atau0J)            */
     double atau0;              /* for xcrit_mode 1                                    */
     int32_t recoil;            /* include the recoil term g (eq. x_f)                 */
     int32_t isotropic;         /* isotropic phase function instead of eq. phaseW       */
@@ -109,6 +110,7 @@ double orc_uniform(uint64_t seed, uint64_t photon, uint64_t k);
 double orc_H(double a, double x);
 double orc_xcw(double a);
 double orc_xcrit(double atau0);
+double orc_atau_jeans(double T, double n_HI);
 void   orc_cell_constants(double T, double n_HI, double *a, double *sigma0, double *k0,
                           double *vth, double *xcw, double *g);
 /* Samplers driven by the photon stream (seed, photon) starting at draw k;
@@ -120,6 +122,15 @@ double orc_sample_upar_one(double a, double x, double xcw, uint64_t seed, uint64
 void orc_sample_uperp(double xcrit_eff, uint64_t seed, int64_t n, double *out2);
 void orc_sample_mu(double rW, uint64_t seed, int64_t n, double *out);
 double orc_upar_split(double a, double x, double xcw, double *u0);
+/* x_crit of an H I scattering at r (moving along k, comoving frequency x) as
+ * the transport computes it for the job's mode; -1 outside the domain. */
+double orc_xcrit_at(const orc_grid *g, const orc_params *p, const double r[3],
+                    const double k[3], double x);
+/* One H I scattering as the transport performs it (stream (seed, photon) from
+ * draw 0, gas at temperature T, core-skipping frequency xcrit as used). */
+void orc_scatter_once(double T, double x, const double k_in[3], double xcrit, int recoil,
+                      int isotropic, uint64_t seed, uint64_t photon, double *x_f,
+                      double k_f[3], double *u_par);
 
 #ifdef __cplusplus
 }

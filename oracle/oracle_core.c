@@ -113,6 +113,14 @@ double orc_xcrit(double atau0)
     return cbrt(atau0) / 5.0;
 }
 
+/* Jeans estimate of a*tau0 for core-skipping (Sec. 3.2.4, eq. atau0J): the
+ * optical depth parameter across one Jeans length of primordial gas of the
+ * cell's density and temperature, 6.428e4 T4^(-1/2) (n_HI / cm^-3)^(1/2). */
+double orc_atau_jeans(double T, double n_HI)
+{
+    return 6.428e4 / sqrt(T / 1.0e4) * sqrt(n_HI);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Parallel atom velocity (Sec. 3.2.3).  Target f(u) ~ exp(-u^2)/(a^2+(x-u)^2) */
 /* (eq. uparf).  For |x| <= 1: Lorentzian proposal, accept exp(-u^2).  For    */

@@ -27,10 +27,41 @@
 #include <stdlib.h>
 #include <string.h>
 
-/* Per-cell quantities derived once from (n_HI, T, v, k_dust) (Sec. 2). */
+/* Per-cell quantities derived once from (n_HI, T, v, k_dust) (Sec. 2), with
+ * the non-local and Jeans a*tau of Sec. 3.2.4. */
 typedef struct {
-    double *a, *k0, *vth, *xcw, *g, *kd, *v, *atau_nl;
+    double *a, *k0, *vth, *xcw, *g, *kd, *v, *atau_nl, *atau_j;
 } orc_cells;
+
+static int64_t n_cells_of(const orc_grid *g)
+{
+    return (g->kind == 0) ? (int64_t)g->nx * g->ny * g->nz : g->n_nodes;
+}
+
+static void cells_init(const orc_grid *g, orc_cells *C)
+{
+    int64_t nc = n_cells_of(g);
+    C->a = calloc(nc, sizeof(double));   C->k0 = calloc(nc, sizeof(double));
+    C->vth = calloc(nc, sizeof(double)); C->xcw = calloc(nc, sizeof(double));
+    C->g = calloc(nc, sizeof(double));   C->kd = calloc(nc, sizeof(double));
+    C->v = calloc(3 * nc, sizeof(double)); C->atau_nl = calloc(nc, sizeof(double));
+    C->atau_j = calloc(nc, sizeof(double));
+    for (int64_t i = 0; i < nc; ++i) {
+        double sigma0;
+        orc_cell_constants(g->T[i], g->n_HI[i], &C->a[i], &sigma0, &C->k0[i], &C->vth[i],
+                           &C->xcw[i], &C->g[i]);
+        C->kd[i] = g->k_dust ? g->k_dust[i] : 0.0;
+        C->atau_nl[i] = g->atau_nl ? g->atau_nl[i] : 0.0;
+        C->atau_j[i] = orc_atau_jeans(g->T[i], g->n_HI[i]);
+        for (int d = 0; d < 3; ++d) C->v[3 * i + d] = g->v ? g->v[3 * i + d] : 0.0;
+    }
+}
+
+static void cells_free(orc_cells *C)
+{
+    free(C->a); free(C->k0); free(C->vth); free(C->xcw); free(C->g); free(C->kd);
+    free(C->v); free(C->atau_nl); free(C->atau_j);
+}
 
 typedef struct {
     double *spectrum, *cam_spec, *cam_img;
@@ -140,6 +171,65 @@ static void isotropic_dir(orc_stream *s, double k[3])
     k[0] = st * cos(phi); k[1] = st * sin(phi); k[2] = mu;
 }
 
+/* Core-skipping frequency at an H I scattering (Sec. 3.2.4): eq. xcrit of the
+ * a*tau0 the job's mode names -- 1: the job's global value; 2: the local
+ * a*tau_cell of eq. atau0min, with l_cell the shortest distance from the
+ * scattering point to the boundary of its cell, plus the cell's non-local
+ * estimate (eq. atauNL); 3: the Jeans estimate of eq. atau0J from the cell's
+ * density and temperature -- and no cut-off for a photon already in the wing
+ * (|x| >= x_cw). */
+static double event_xcrit(const orc_params *p, const orc_cells *C, int64_t ci,
+                          const orc_cell *c, const double r[3], double x)
+{
+    double xcrit = 0.0;
+    if (p->xcrit_mode == 1) {
+        xcrit = orc_xcrit(p->atau0);
+    } else if (p->xcrit_mode == 2) {
+        double l_cell = orc_min_face_distance(c, r);
+        xcrit = orc_xcrit(C->a[ci] * C->k0[ci] * l_cell + C->atau_nl[ci]);
+    } else if (p->xcrit_mode == 3) {
+        xcrit = orc_xcrit(C->atau_j[ci]);
+    }
+    if (fabs(x) >= C->xcw[ci]) xcrit = 0.0;
+    return xcrit;
+}
+
+/* What one H I scattering leaves: the parallel atom velocity, the atom
+ * velocity vector, the phase-function parameter r_W used, the new direction
+ * and the redistributed comoving frequency. */
+typedef struct {
+    double u_par, u_atom[3], rW, kf[3], x_f;
+    int64_t tries;
+} orc_scatter;
+
+/* One H I scattering (Sec. 3.1.3) of a photon of comoving frequency x moving
+ * along k in a cell with damping a, crossover x_cw and recoil parameter g_rec
+ * (0 when recoil is off): u_par by rejection (Sec. 3.2.3), the perpendicular
+ * components truncated below xcrit (Sec. 3.2.4), the direction from the phase
+ * function of eq. phaseW about k (core mixture for |x| < x_cw, wing dipole
+ * otherwise, or isotropic), and x_f of eq. x_f.  Draw order: u_par, u_perp
+ * (2), mu, phi. */
+static void scatter_hi(double a, double xcw, double g_rec, double xcrit, int isotropic,
+                       double x, const double k[3], orc_stream *st, orc_scatter *o)
+{
+    o->tries = 0;
+    o->u_par = orc_draw_upar(a, x, xcw, st, &o->tries);
+    double u1, u2;
+    orc_draw_uperp(xcrit, st, &u1, &u2);
+    double e1[3], e2[3];
+    orc_perp_basis(k, e1, e2);
+    for (int d = 0; d < 3; ++d) o->u_atom[d] = o->u_par * k[d] + u1 * e1[d] + u2 * e2[d];
+    o->rW = isotropic ? 0.0 : ((fabs(x) < xcw) ? 3.0 / 11.0 : 1.0);
+    double mu = orc_draw_mu(o->rW, st);
+    double phi = 2.0 * ORC_PI * orc_draw(st);
+    double st_ = sqrt(1.0 - mu * mu);
+    for (int d = 0; d < 3; ++d)
+        o->kf[d] = mu * k[d] + st_ * (cos(phi) * e1[d] + sin(phi) * e2[d]);
+    double nk = sqrt(dot3(o->kf, o->kf));
+    for (int d = 0; d < 3; ++d) o->kf[d] /= nk;
+    o->x_f = x - o->u_par + dot3(o->kf, o->u_atom) + g_rec * (mu - 1.0);   /* eq. x_f */
+}
+
 static void run_photon(orc_job *J, uint64_t id, orc_tally *T)
 {
     const orc_grid *g = J->g;
@@ -241,48 +331,26 @@ static void run_photon(orc_job *J, uint64_t id, orc_tally *T)
 
         /* H I scattering (Sec. 3.1.3) */
         double a = C->a[ci], xcw = C->xcw[ci];
-        int64_t tries = 0;
-        double u_par = orc_draw_upar(a, x, xcw, &st, &tries);
-        T->counters[ORC_UPAR_TRIES] += (uint64_t)tries;
-        double xcrit = 0.0;                     /* core-skipping (Sec. 3.2.4) */
-        if (p->xcrit_mode == 1) {
-            xcrit = orc_xcrit(p->atau0);
-        } else if (p->xcrit_mode == 2) {
-            double atau = a * C->k0[ci] * orc_min_face_distance(&c, r) + C->atau_nl[ci];
-            xcrit = orc_xcrit(atau);
-        }
-        if (fabs(x) >= xcw) xcrit = 0.0;        /* already in the wing: no cut-off */
-        double u1, u2;
-        orc_draw_uperp(xcrit, &st, &u1, &u2);
-        double e1[3], e2[3];
-        orc_perp_basis(k, e1, e2);
-        double u_atom[3];
-        for (int d = 0; d < 3; ++d) u_atom[d] = u_par * k[d] + u1 * e1[d] + u2 * e2[d];
-        double rW = p->isotropic ? 0.0 : ((fabs(x) < xcw) ? 3.0 / 11.0 : 1.0);
-        double mu = orc_draw_mu(rW, &st);
-        double phi = 2.0 * ORC_PI * orc_draw(&st);
-        double st_ = sqrt(1.0 - mu * mu);
-        double kf[3];
-        for (int d = 0; d < 3; ++d)
-            kf[d] = mu * k[d] + st_ * (cos(phi) * e1[d] + sin(phi) * e2[d]);
-        double nk = sqrt(dot3(kf, kf));
-        for (int d = 0; d < 3; ++d) kf[d] /= nk;
         double g_rec = p->recoil ? C->g[ci] : 0.0;
-        double x_f = x - u_par + dot3(kf, u_atom) + g_rec * (mu - 1.0);   /* eq. x_f */
+        /* x_crit does not depend on u_par's draws, so it may be taken first */
+        double xcrit = event_xcrit(p, C, ci, &c, r, x);
+        orc_scatter sc;
+        scatter_hi(a, xcw, g_rec, xcrit, p->isotropic, x, k, &st, &sc);
+        T->counters[ORC_UPAR_TRIES] += (uint64_t)sc.tries;
         nscat += 1;
         T->counters[ORC_SCAT_HI] += 1;
         if (p->n_cams > 0) {
-            double wn = 1.0 + rW / 3.0;
+            double wn = 1.0 + sc.rW / 3.0;
             for (int i = 0; i < p->n_cams; ++i) {
                 const double *dc = &p->cam_dir[3 * i];
                 double muc = dot3(k, dc);
-                W[i] = (1.0 + rW * muc * muc) / wn;
-                xcam[i] = x - u_par + dot3(dc, u_atom) + g_rec * (muc - 1.0);
+                W[i] = (1.0 + sc.rW * muc * muc) / wn;
+                xcam[i] = x - sc.u_par + dot3(dc, sc.u_atom) + g_rec * (muc - 1.0);
             }
             peel_off(J, &c, r, xcam, W, T, rec_peel);
         }
-        for (int d = 0; d < 3; ++d) k[d] = kf[d];
-        x_lab = lab_x(C, ci, x_f, k);
+        for (int d = 0; d < 3; ++d) k[d] = sc.kf[d];
+        x_lab = lab_x(C, ci, sc.x_f, k);
         tau = -log(orc_draw(&st));
     }
     if (status == 1) T->counters[ORC_ESCAPED] += 1;
@@ -321,25 +389,13 @@ static void *worker(void *arg)
 int orc_run(const orc_grid *g, const orc_source *s, const orc_params *p, orc_out *o,
             int n_threads)
 {
-    if (p->n_cams > 64 || p->id_end < p->id_begin) return -1;
+    if (p->n_cams > 64 || p->id_end < p->id_begin || p->xcrit_mode < 0 || p->xcrit_mode > 3)
+        return -1;
     if (g->kind == 1 && !g->child) return -1;
-    int64_t nc = (g->kind == 0) ? (int64_t)g->nx * g->ny * g->nz : g->n_nodes;
     orc_job J;
     memset(&J, 0, sizeof J);
     J.g = g; J.s = s; J.p = p; J.o = o;
-    orc_cells *C = &J.cells;
-    C->a = calloc(nc, sizeof(double));   C->k0 = calloc(nc, sizeof(double));
-    C->vth = calloc(nc, sizeof(double)); C->xcw = calloc(nc, sizeof(double));
-    C->g = calloc(nc, sizeof(double));   C->kd = calloc(nc, sizeof(double));
-    C->v = calloc(3 * nc, sizeof(double)); C->atau_nl = calloc(nc, sizeof(double));
-    for (int64_t i = 0; i < nc; ++i) {
-        double sigma0;
-        orc_cell_constants(g->T[i], g->n_HI[i], &C->a[i], &sigma0, &C->k0[i], &C->vth[i],
-                           &C->xcw[i], &C->g[i]);
-        C->kd[i] = g->k_dust ? g->k_dust[i] : 0.0;
-        C->atau_nl[i] = g->atau_nl ? g->atau_nl[i] : 0.0;
-        for (int d = 0; d < 3; ++d) C->v[3 * i + d] = g->v ? g->v[3 * i + d] : 0.0;
-    }
+    cells_init(g, &J.cells);
     for (int d = 0; d < 3; ++d) J.centre[d] = 0.5 * (g->box_min[d] + g->box_max[d]);
     for (int i = 0; i < p->n_cams; ++i) {           /* camera image axes */
         const double *dc = &p->cam_dir[3 * i];
@@ -391,7 +447,39 @@ int orc_run(const orc_grid *g, const orc_source *s, const orc_params *p, orc_out
         free(T->spectrum); free(T->cam_spec); free(T->cam_img);
     }
     free(J.tallies); free(th); free(args); free(J.src_cdf);
-    free(C->a); free(C->k0); free(C->vth); free(C->xcw); free(C->g); free(C->kd);
-    free(C->v); free(C->atau_nl);
+    cells_free(&J.cells);
     return 0;
+}
+
+/* x_crit at an H I scattering of comoving frequency x at r, moving along k,
+ * as the transport computes it (event_xcrit); -1 if r is outside the domain. */
+double orc_xcrit_at(const orc_grid *g, const orc_params *p, const double r[3],
+                    const double k[3], double x)
+{
+    orc_cell c;
+    if (!orc_locate(g, r, k, &c)) return -1.0;
+    orc_cells C;
+    cells_init(g, &C);
+    double xc = event_xcrit(p, &C, c.id, &c, r, x);
+    cells_free(&C);
+    return xc;
+}
+
+/* One H I scattering as the transport performs it (scatter_hi), for a photon
+ * of comoving frequency x moving along the unit vector k_in in gas at
+ * temperature T, with core-skipping frequency xcrit (as used: the wing rule
+ * already applied), recoil on or off, from stream (seed, photon) at draw 0.
+ * Outputs x_f, k_f and u_par. */
+void orc_scatter_once(double T, double x, const double k_in[3], double xcrit, int recoil,
+                      int isotropic, uint64_t seed, uint64_t photon, double *x_f,
+                      double k_f[3], double *u_par)
+{
+    double a, sigma0, k0, vth, xcw, g;
+    orc_cell_constants(T, 1.0, &a, &sigma0, &k0, &vth, &xcw, &g);
+    orc_stream st = { seed, photon, 0 };
+    orc_scatter sc;
+    scatter_hi(a, xcw, recoil ? g : 0.0, xcrit, isotropic, x, k_in, &st, &sc);
+    *x_f = sc.x_f;
+    for (int d = 0; d < 3; ++d) k_f[d] = sc.kf[d];
+    *u_par = sc.u_par;
 }
