@@ -27,13 +27,21 @@
  *   - Descriptor and array arguments are HOST pointers, borrowed for the call
  *     only; data is copied to the device.  Handles are owned by the library
  *     until released.  Output buffers of colt_tally are owned by the caller.
- *   - Device memory comes from the supplied allocator (NULL = hipMalloc).
+ *   - Device memory of grids, jobs, launch tables and graphs comes from the
+ *     allocator given to colt_init_grid (NULL = hipMalloc); the device checks
+ *     at the end of this file allocate their temporaries with hipMalloc.
  *   - `stream` is a hipStream_t (NULL = default stream).  Calls are
  *     asynchronous on it unless stated otherwise.
  *   - Random numbers: photon i of a job draws uniform number k from
  *     Philox4x32-10 (Salmon et al. 2011) with key = job seed (64 bit) and
  *     counter = (block lo, block hi, i lo, i hi), one draw order per photon;
- *     results do not depend on launch shape or job batching.
+ *     results do not depend on launch shape, job batching, kernel variant or
+ *     where a launch was stopped.
+ *   - Preemption: a transport launch can stop at the end of a pass of its
+ *     wave loop (colt_stop_set, or a camera job's next-event task buffer near
+ *     full).  Photons in flight are then suspended in the job's device memory
+ *     and the next launch of the job resumes them first; every photon's
+ *     history and every tally equal those of an uninterrupted run.
  */
 #ifndef COLT_H
 #define COLT_H
@@ -129,7 +137,8 @@ typedef struct {
     uint64_t seed;
     int32_t precision;                    /* COLT_FP64 or COLT_FP32_BULK          */
     int32_t xcrit_mode;                   /* 0 off; 1 global: x_crit(atau0);      */
-                                          /* 2 local: a tau_cell + atau_nl[cell]  */
+                                          /* 2 local: a tau_cell + atau_nl[cell]; */
+                                          /* 3 Jeans: a tau_J of the cell         */
     double atau0;                         /* a*tau0 for xcrit_mode 1              */
     int32_t recoil;                       /* recoil term g(mu - 1) of eq. x_f     */
     int32_t isotropic;                    /* 1: isotropic H I scattering          */
@@ -144,11 +153,14 @@ typedef struct {
     double tau_peel_max;                  /* next-event cut-off (paper: 50)       */
     int32_t record;                       /* 1: keep per-photon records           */
     uint64_t max_events;                  /* per-photon event cap; 0 = 2^62       */
+    uint64_t march_tasks;                 /* next-event task slots (cameras); 0 = */
+                                          /* sized from n_photons and n_cams      */
 } colt_job_params;
 
 /* Launch shape of colt_transport; NULL or zero fields take defaults. */
 typedef struct {
-    int32_t block;                        /* threads per workgroup (64..1024)     */
+    int32_t block;                        /* threads per workgroup: 64, 128, 192  */
+                                          /* or 256 (0 = 256)                     */
     int32_t blocks_per_cu;                /* resident workgroups per CU (grid size) */
     uint64_t photons_per_job;             /* photons taken from each job per call; */
                                           /* 0 = all that remain                   */
@@ -160,6 +172,8 @@ typedef struct {
                                           /* photons, a quarter of them); 0 =      */
                                           /* default (16), 1 = every flight ends   */
                                           /* within its pass                       */
+    int32_t stop_token;                   /* 1..63: the launch stops when          */
+                                          /* colt_stop_set(token, 1); 0 = none     */
 } colt_launch;
 
 typedef struct {
@@ -194,21 +208,47 @@ colt_status colt_init_grid(const colt_grid_desc *desc, const colt_allocator *all
  * COLT_ERR_STATE (jobs registered on the grid), COLT_ERR_HIP. */
 colt_status colt_grid_nonlocal(colt_grid grid, double f_nl, void *stream);
 
-/* Registers a transfer job on a grid: sources, photon count, physics options
- * and tally layout.  Allocates and zeroes the job's device tallies on the
- * grid's stream.  The job keeps a reference to the grid.
- * Errors: COLT_ERR_ARG, COLT_ERR_NOMEM, COLT_ERR_HIP. */
+/* Registers a transfer job on a grid: the emission of Sec. 3.1.1 (sources,
+ * N_ph photon packets of equal weight, each with an isotropic direction and
+ * the frequency of eq. init_freq or x = 0), the physics options of Secs.
+ * 3.1.3 and 3.2.4 (recoil, phase function, core-skipping mode) and the tally
+ * layout of Sec. 6.1 (observers, spectral and image bins).  Photon i is
+ * generated lazily by the transport from (seed, i).  Allocates and zeroes the
+ * job's device tallies, its control block, two suspend arrays of min(N_ph,
+ * resident lanes) records and, with cameras, its next-event task buffer, on
+ * the grid's stream.  The job keeps a reference to the grid.  `src` and `p`
+ * are borrowed for the call.
+ * Errors: COLT_ERR_ARG (invalid option or source), COLT_ERR_NOMEM, COLT_ERR_HIP. */
 colt_status colt_emit(colt_grid grid, const colt_source_desc *src,
                       const colt_job_params *params, colt_job *out);
 
 /* Transports photons of n_jobs jobs in one persistent launch per precision
- * mode on `stream` (asynchronous).  Each job contributes its next
- * `photons_per_job` photons (all remaining if 0); lanes that finish a photon
- * take the next one from a shared queue, so jobs of uneven cost share the
- * device.  Errors: COLT_ERR_ARG, COLT_ERR_STATE (a job already complete),
+ * mode on `stream` (asynchronous): each photon is traced cell by cell against
+ * its optical depth drawn by eq. lnR, with the Doppler and temperature
+ * frequency transform between cells (Sec. 3.1.2), and scatters off H I with
+ * the atom velocity of Secs. 3.1.3 and 3.2.3, the phase function eq. phaseW,
+ * the redistribution eq. x_f and core-skipping (Sec. 3.2.4), or off grey dust,
+ * until it escapes or is absorbed; every event adds its next-event estimate
+ * for each camera (Sec. 6.1).  Each job first resumes its suspended photons,
+ * then contributes its next `photons_per_job` new photons (all remaining if
+ * 0); lanes that finish a photon take the next one from a shared queue, so
+ * jobs of uneven cost share the device.  The launch is planned on the device
+ * from each job's control block.  A launch may stop early (stop_token, or a
+ * camera job's task buffer near full): its photons in flight are suspended and
+ * colt_job_status reports the job unfinished until a later launch completes
+ * it.  A launch that can stop, and any launch of a job a stopped launch may
+ * have left unfinished, waits for the job's launches on other streams.  `jobs`
+ * is borrowed for the call.  Errors: COLT_ERR_ARG (list, block, token or a
+ * task buffer too small for one wave), COLT_ERR_NOMEM (launch table),
  * COLT_ERR_HIP. */
 colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
                            void *stream);
+
+/* Sets (value != 0) or clears the stop word `token` (1..63).  Transport
+ * launches started with that stop_token stop within about 32 passes of their
+ * wave loop, suspending their photons in flight; a launch started while the
+ * word is set does one pass and stops.  Errors: COLT_ERR_ARG, COLT_ERR_NOMEM. */
+colt_status colt_stop_set(int32_t token, int32_t value);
 
 /* Captures one transport epoch over n_jobs jobs (one precision) into a HIP
  * graph: a planning kernel takes up to photons_per_job photons (all if 0) from
@@ -225,17 +265,38 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
 colt_status colt_graph_launch(colt_graph graph, void *stream);
 void colt_graph_release(colt_graph graph);
 
-/* Copies a job's tallies to caller buffers (sizes from its params).  With
- * wait = 1 it first synchronises the job's last stream; with wait = 0 it
- * returns COLT_ERR_BUSY if work is still in flight. */
+/* Copies a job's tallies to caller buffers (sizes from its params): the
+ * angle-averaged escape spectrum of Sec. 4 (photon counts per lab-frame
+ * frequency bin, with under- and overflow), each camera's spectrum and
+ * orthographic image of summed W exp(-tau_esc) (Sec. 6.1, eq. SB: multiply by
+ * L/(4 pi N_ph d_L^2 Omega_pix) for surface brightness), the event counters
+ * and, for record = 1 jobs, the per-photon records.  With wait = 1 it first
+ * waits for every launch of the job (on every stream); with wait = 0 it
+ * returns COLT_ERR_BUSY if any is still running.  Tallies of a job with
+ * suspended photons cover the work done so far.  Errors: COLT_ERR_ARG,
+ * COLT_ERR_BUSY, COLT_ERR_STATE (suspended photons or next-event marches
+ * found no room: the results are incomplete), COLT_ERR_HIP. */
 colt_status colt_tally(colt_job job, colt_tally_out *out, int32_t wait);
 
-/* Photons handed to transport so far and the job's total. */
+/* Photons taken by transport and not suspended (*launched), and the job's
+ * total; the job is complete once every launch has ended and *launched ==
+ * *total.  Exact without waiting unless a launch that can stop ran since the
+ * last call; then it waits for the job's launches. */
 colt_status colt_job_status(colt_job job, uint64_t *launched, uint64_t *total);
+
+/* Unfinished photons of a job (waits for its launches): ids >= *next_id were
+ * never started, and *n_suspended photons wait to resume; their ids (up to
+ * ids_cap of them, sorted) go to `ids` when it is not NULL. */
+colt_status colt_job_pending(colt_job job, uint64_t *next_id, uint64_t *n_suspended,
+                             uint64_t *ids, uint64_t ids_cap);
 
 /* Device bytes held by a grid or a job (for admission control). */
 size_t colt_grid_bytes(colt_grid grid);
 size_t colt_job_bytes(colt_job job);
+/* Device bytes colt_emit would allocate for a job with these parameters and
+ * n_src sources (0 for invalid arguments); exact for the library's own
+ * allocations, before the allocator's rounding. */
+size_t colt_job_footprint(const colt_job_params *p, int32_t n_src);
 
 /* Duration in ms of the last transport kernel launched with time_kernel = 1
  * on the calling thread (synchronises on its end event); < 0 if none. */
@@ -248,9 +309,9 @@ const char *colt_last_error(void);
 
 /* ---- device checks of the building blocks (host arrays in and out) ---- */
 
-/* Per-cell derived fields as computed on the device, 10 doubles per cell:
+/* Per-cell derived fields as computed on the device, 11 doubles per cell:
  * k0 (cm^-1), a, v_th (km/s), u_x, u_y, u_z (bulk velocity / v_th),
- * k_dust (cm^-1), x_cw, g, atau_nl. */
+ * k_dust (cm^-1), x_cw, g, atau_nl, atau_J (eq. atau0J). */
 colt_status colt_grid_fields(colt_grid grid, double *out);
 
 /* H(a, x) (eq. AB) evaluated on the device in the given precision. */

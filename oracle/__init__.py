@@ -58,17 +58,19 @@ class _Out(ctypes.Structure):
                 ("rec_peel", _dp), ("rec_len", _dp)]
 
 
-_lib = None
+_libs = {}
+_LIB_FMA = os.path.join(_HERE, "liborc_fma.so")
 
 
-def lib():
-    """Loads liborc.so, building it first if it is missing."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def lib(variant=""):
+    """Loads liborc.so (variant "fma": the same sources built with fused
+    multiply-adds), building them first if missing."""
+    if variant not in _libs:
+        path = _LIB_FMA if variant == "fma" else _LIB
+        if not os.path.exists(path):
             from . import build as _b
             _b.build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         L.orc_run.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Source),
                               ctypes.POINTER(_Params), ctypes.POINTER(_Out), ctypes.c_int]
         L.orc_run.restype = ctypes.c_int
@@ -104,8 +106,8 @@ def lib():
                                        ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                        ctypes.c_uint64, _dp, _dp, _dp]
         L.orc_scatter_once.restype = None
-        _lib = L
-    return _lib
+        _libs[variant] = L
+    return _libs[variant]
 
 
 def _ptr(a, ctype=_dp):
@@ -286,7 +288,8 @@ def _params_struct(params, id_begin, id_end, hold):
     return p
 
 
-def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=None):
+def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=None,
+        variant=""):
     """Runs photons [id_begin, id_end) of a job through the oracle.
 
     Returns a dict with the escape spectrum (under/overflow at both ends), the
@@ -338,8 +341,8 @@ def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=No
         o.rec_pos = _ptr(rec["pos"])
         o.rec_peel = _ptr(rec["peel"]) if n_cams else None
         o.rec_len = _ptr(rec["len"])
-    rc = lib().orc_run(ctypes.byref(g), ctypes.byref(s), ctypes.byref(p), ctypes.byref(o),
-                       int(threads))
+    rc = lib(variant).orc_run(ctypes.byref(g), ctypes.byref(s), ctypes.byref(p),
+                              ctypes.byref(o), int(threads))
     if rc != 0:
         raise RuntimeError(f"oracle run failed ({rc})")
     counters = {name: int(o.counters[i]) for i, name in enumerate(COUNTER_NAMES)}

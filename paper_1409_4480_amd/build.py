@@ -10,8 +10,12 @@ SOURCES = ["colt_kernels.hip", "colt_api.cpp"]
 ARCH = os.environ.get("COLT_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled: the compiler would otherwise form
-# v_pk_* FP32 arithmetic from scalar code.
+# v_pk_* FP32 arithmetic from scalar code.  Multiply-adds are fused only within
+# one expression (-ffp-contract=on), so every kernel variant rounds a given
+# expression the same way and FP32 histories do not depend on which variant
+# (one job or several, grid kind) ran them.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
+             "-ffp-contract=on",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-command-line-argument"]
 

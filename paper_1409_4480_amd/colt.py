@@ -25,7 +25,7 @@ EXPORTS = ["colt_init_grid", "colt_emit", "colt_transport", "colt_tally", "colt_
            "colt_grid_bytes", "colt_job_bytes", "colt_last_kernel_ms", "colt_release_job",
            "colt_release_grid", "colt_last_error", "colt_grid_fields", "colt_eval_voigt",
            "colt_sample", "colt_grid_nonlocal", "colt_graph_create", "colt_graph_launch",
-           "colt_graph_release"]
+           "colt_graph_release", "colt_stop_set", "colt_job_pending", "colt_job_footprint"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -65,13 +65,13 @@ class JobParams(ctypes.Structure):
                 ("cam_xmin", ctypes.c_double), ("cam_xmax", ctypes.c_double),
                 ("cam_npix", ctypes.c_int32), ("cam_fov", ctypes.c_double),
                 ("tau_peel_max", ctypes.c_double), ("record", ctypes.c_int32),
-                ("max_events", ctypes.c_uint64)]
+                ("max_events", ctypes.c_uint64), ("march_tasks", ctypes.c_uint64)]
 
 
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("photons_per_job", ctypes.c_uint64), ("time_kernel", ctypes.c_int32),
-                ("march_min", ctypes.c_int32)]
+                ("march_min", ctypes.c_int32), ("stop_token", ctypes.c_int32)]
 
 
 class TallyOut(ctypes.Structure):
@@ -120,6 +120,12 @@ def lib():
         L.colt_graph_launch.argtypes = [vp, vp]
         L.colt_graph_release.argtypes = [vp]
         L.colt_graph_release.restype = None
+        L.colt_stop_set.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.colt_job_footprint.argtypes = [ctypes.POINTER(JobParams), ctypes.c_int32]
+        L.colt_job_footprint.restype = ctypes.c_size_t
+        L.colt_job_pending.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64]
         L.colt_eval_voigt.argtypes = [ctypes.c_int32, _dp, _dp, ctypes.c_int64, _dp, vp]
         L.colt_sample.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
@@ -127,7 +133,8 @@ def lib():
         for name in ("colt_init_grid", "colt_emit", "colt_transport", "colt_tally",
                      "colt_job_status", "colt_release_grid", "colt_grid_fields",
                      "colt_eval_voigt", "colt_sample", "colt_grid_nonlocal",
-                     "colt_graph_create", "colt_graph_launch"):
+                     "colt_graph_create", "colt_graph_launch", "colt_stop_set",
+                     "colt_job_pending"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -243,9 +250,9 @@ class Grid:
         return int(lib().colt_grid_bytes(self.handle))
 
     def fields(self):
-        """Device-derived per-cell fields, (n_cells, 10): k0, a, v_th, u (3),
-        k_dust, x_cw, g, atau_nl."""
-        out = np.zeros((self.n_leaves, 10))
+        """Device-derived per-cell fields, (n_cells, 11): k0, a, v_th, u (3),
+        k_dust, x_cw, g, atau_nl, atau_J."""
+        out = np.zeros((self.n_leaves, 11))
         _check(lib().colt_grid_fields(self.handle, _ptr(out)))
         return out
 
@@ -255,48 +262,65 @@ class Grid:
             self.handle = None
 
 
+def _job_descs(source, params, precision=FP64, record=False, max_events=0, march_tasks=0):
+    """C descriptors of a job's sources and parameters (and the arrays they
+    point to, which must outlive them)."""
+    s = SourceDesc()
+    pos = _f64(source["pos"])
+    s.kind = int(source["kind"])
+    s.n_src = pos.size // 3
+    s.pos = _ptr(pos)
+    w = _f64(source.get("weight"))
+    s.weight = _ptr(w)
+    s.sigma = float(source.get("sigma", 0.0))
+    s.freq_mode = int(source.get("freq_mode", 0))
+    p = JobParams()
+    p.n_photons = int(params["n_photons"])
+    p.seed = int(params["seed"])
+    p.precision = int(precision)
+    p.xcrit_mode = int(params.get("xcrit_mode", 0))
+    p.atau0 = float(params.get("atau0", 0.0))
+    p.recoil = int(params.get("recoil", 0))
+    p.isotropic = int(params.get("isotropic", 0))
+    p.n_bins = int(params.get("n_bins", 0))
+    p.x_min = float(params.get("x_min", -1.0))
+    p.x_max = float(params.get("x_max", 1.0))
+    cams = params.get("cam_dir")
+    cams = None if cams is None else _f64(cams)
+    n_cams = 0 if cams is None else cams.size // 3
+    p.n_cams = n_cams
+    p.cam_dir = _ptr(cams)
+    p.cam_nbins = int(params.get("cam_nbins", 0)) if n_cams else 0
+    p.cam_xmin = float(params.get("cam_xmin", -1.0))
+    p.cam_xmax = float(params.get("cam_xmax", 1.0))
+    p.cam_npix = int(params.get("cam_npix", 0)) if n_cams else 0
+    p.cam_fov = float(params.get("cam_fov", 1.0))
+    p.tau_peel_max = float(params.get("tau_peel_max", 50.0))
+    p.record = int(bool(record))
+    p.max_events = int(max_events)
+    p.march_tasks = int(march_tasks or params.get("march_tasks", 0))
+    return s, p, (pos, w, cams)
+
+
+def job_footprint(source, params, precision=FP64, record=False):
+    """Device bytes the library allocates for a job of these parameters."""
+    s, p, keep = _job_descs(source, params, precision, record)
+    return int(lib().colt_job_footprint(ctypes.byref(p), int(s.n_src)))
+
+
 class Job:
     """A transfer job registered on a grid."""
 
-    def __init__(self, grid, source, params, precision=FP64, record=False, max_events=0):
+    def __init__(self, grid, source, params, precision=FP64, record=False, max_events=0,
+                 march_tasks=0):
         L = lib()
-        s = SourceDesc()
-        pos = _f64(source["pos"])
-        s.kind = int(source["kind"])
-        s.n_src = pos.size // 3
-        s.pos = _ptr(pos)
-        w = _f64(source.get("weight"))
-        s.weight = _ptr(w)
-        s.sigma = float(source.get("sigma", 0.0))
-        s.freq_mode = int(source.get("freq_mode", 0))
-        p = JobParams()
-        p.n_photons = int(params["n_photons"])
-        p.seed = int(params["seed"])
-        p.precision = int(precision)
-        p.xcrit_mode = int(params.get("xcrit_mode", 0))
-        p.atau0 = float(params.get("atau0", 0.0))
-        p.recoil = int(params.get("recoil", 0))
-        p.isotropic = int(params.get("isotropic", 0))
-        p.n_bins = int(params.get("n_bins", 0))
-        p.x_min = float(params.get("x_min", -1.0))
-        p.x_max = float(params.get("x_max", 1.0))
-        cams = params.get("cam_dir")
-        cams = None if cams is None else _f64(cams)
-        self.n_cams = 0 if cams is None else cams.size // 3
-        p.n_cams = self.n_cams
-        p.cam_dir = _ptr(cams)
-        p.cam_nbins = int(params.get("cam_nbins", 0)) if self.n_cams else 0
-        p.cam_xmin = float(params.get("cam_xmin", -1.0))
-        p.cam_xmax = float(params.get("cam_xmax", 1.0))
-        p.cam_npix = int(params.get("cam_npix", 0)) if self.n_cams else 0
-        p.cam_fov = float(params.get("cam_fov", 1.0))
-        p.tau_peel_max = float(params.get("tau_peel_max", 50.0))
-        p.record = int(bool(record))
-        p.max_events = int(max_events)
+        s, p, keep = _job_descs(source, params, precision, record, max_events, march_tasks)
+        self.n_cams = int(p.n_cams)
         h = ctypes.c_void_p()
         _check(L.colt_emit(grid.handle, ctypes.byref(s), ctypes.byref(p), ctypes.byref(h)))
         self.handle = h
         self.params = p
+        self._keep = keep
         self.grid = grid
 
     @property
@@ -304,9 +328,25 @@ class Job:
         return int(lib().colt_job_bytes(self.handle))
 
     def status(self):
+        """(photons taken and not suspended, total); complete when equal and
+        no launch is running."""
         a, b = ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().colt_job_status(self.handle, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    @property
+    def complete(self):
+        a, b = self.status()
+        return a == b
+
+    def pending(self, max_ids=0):
+        """(next never-started id, suspended count, sorted suspended ids)."""
+        nxt, ns = ctypes.c_uint64(), ctypes.c_uint64()
+        ids = np.zeros(max(int(max_ids), 1), np.uint64)
+        _check(lib().colt_job_pending(self.handle, ctypes.byref(nxt), ctypes.byref(ns),
+                                      ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                      int(max_ids)))
+        return nxt.value, ns.value, ids[:min(int(max_ids), ns.value)]
 
     def tally(self, wait=True):
         p = self.params
@@ -339,13 +379,14 @@ class Job:
 
 
 def transport(jobs, block=0, blocks_per_cu=0, photons_per_job=0, time_kernel=False,
-              stream=None, march_min=0):
+              stream=None, march_min=0, stop_token=0):
     """Runs (the next slice of) each job's photons in one persistent launch per
-    precision on the stream (asynchronous)."""
+    precision on the stream (asynchronous).  The launch may stop early (a stop
+    token, or a camera job's task buffer): then call again until complete."""
     jobs = list(jobs)
     arr = (ctypes.c_void_p * max(len(jobs), 1))(*[j.handle for j in jobs])
     lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), int(bool(time_kernel)),
-                int(march_min))
+                int(march_min), int(stop_token))
     _check(lib().colt_transport(arr, len(jobs), ctypes.byref(lc),
                                 stream if stream is not None else current_stream()))
 
@@ -354,12 +395,14 @@ class Graph:
     """One transport epoch over fixed jobs captured as a HIP graph; each
     launch() replays an epoch of up to photons_per_job photons per job."""
 
-    def __init__(self, jobs, photons_per_job=0, block=0, blocks_per_cu=0, march_min=0):
+    def __init__(self, jobs, photons_per_job=0, block=0, blocks_per_cu=0, march_min=0,
+                 stop_token=0):
         torch = _torch()
         self.jobs = list(jobs)
         self._capture = torch.cuda.Stream()
         arr = (ctypes.c_void_p * len(self.jobs))(*[j.handle for j in self.jobs])
-        lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), 0, int(march_min))
+        lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), 0, int(march_min),
+                    int(stop_token))
         h = ctypes.c_void_p()
         torch.cuda.current_stream().synchronize()
         _check(lib().colt_graph_create(arr, len(self.jobs), ctypes.byref(lc),
@@ -375,6 +418,26 @@ class Graph:
         if self.handle:
             lib().colt_graph_release(self.handle)
             self.handle = None
+
+
+def stop_set(token, value=True):
+    """Sets or clears stop word `token` (1..63) polled by launches given it."""
+    _check(lib().colt_stop_set(int(token), int(bool(value))))
+
+
+def transport_all(jobs, max_launches=1_000_000, **kw):
+    """Launches until every job is complete (a launch can stop early when a
+    camera job's next-event task buffer fills); returns the launch count."""
+    jobs = list(jobs)
+    n = 0
+    while True:
+        todo = [j for j in jobs if not j.complete]
+        if not todo:
+            return n
+        if n >= max_launches:
+            raise ColtError(f"jobs not complete after {n} launches")
+        transport(todo, **kw)
+        n += 1
 
 
 def last_kernel_ms():
@@ -413,8 +476,11 @@ def run(workload, precision=FP64, record=False, block=0, blocks_per_cu=0, max_ev
     j = Job(g, workload["source"], workload["params"], precision=precision, record=record,
             max_events=max_events)
     try:
-        transport([j], block=block, blocks_per_cu=blocks_per_cu, march_min=march_min)
-        return j.tally()
+        launches = transport_all([j], block=block, blocks_per_cu=blocks_per_cu,
+                                 march_min=march_min)
+        out = j.tally()
+        out["launches"] = launches
+        return out
     finally:
         j.release()
         g.release()

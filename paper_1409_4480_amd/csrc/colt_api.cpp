@@ -145,39 +145,88 @@ struct DevMem {
     }
 };
 
-// Reusable launch tables: device memory plus pinned host staging, recycled once
-// the event recorded after their launch has completed.
+// Device memory from an allocator (NULL or incomplete: hipMalloc) and its release.
+void *dev_alloc(const colt_allocator &a, bool custom, size_t n)
+{
+    void *p = nullptr;
+    if (custom) return a.alloc(n, a.user);
+    return (hipMalloc(&p, n) == hipSuccess) ? p : nullptr;
+}
+
+void dev_free(const colt_allocator &a, bool custom, void *p)
+{
+    if (!p) return;
+    if (custom) a.free(p, a.user);
+    else (void)hipFree(p);
+}
+
+// Reusable launch tables: device memory from the jobs' allocator plus pinned
+// host staging, recycled once the event recorded after their launch has
+// completed.  Tables are kept per allocator and are never returned to it.
 struct LaunchBuf {
     void *dev = nullptr;
     void *host = nullptr;
     size_t size = 0;
     hipEvent_t done = nullptr;
+    colt_allocator alloc{};
+    bool custom = false;
 };
 std::mutex g_pool_mu;
 std::vector<LaunchBuf *> g_pool;
 
-LaunchBuf *acquire_launch_buf(size_t bytes)
+bool same_allocator(const LaunchBuf *b, const colt_allocator &a, bool custom)
+{
+    if (b->custom != custom) return false;
+    return !custom || (b->alloc.alloc == a.alloc && b->alloc.free == a.free &&
+                       b->alloc.user == a.user);
+}
+
+LaunchBuf *acquire_launch_buf(size_t bytes, const colt_allocator &a, bool custom)
 {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (LaunchBuf *b : g_pool) {
-        if (b->size >= bytes && hipEventQuery(b->done) == hipSuccess) return b;
+        if (b->size >= bytes && same_allocator(b, a, custom) &&
+            hipEventQuery(b->done) == hipSuccess)
+            return b;
     }
     LaunchBuf *b = new LaunchBuf();
-    b->size = std::max<size_t>(bytes, 4096);
-    if (hipMalloc(&b->dev, b->size) != hipSuccess) { delete b; return nullptr; }
+    b->size = std::max<size_t>((bytes + 4095) & ~size_t(4095), 4096);
+    b->alloc = a;
+    b->custom = custom;
+    b->dev = dev_alloc(a, custom, b->size);
+    if (!b->dev) { delete b; return nullptr; }
     if (hipHostMalloc(&b->host, b->size, hipHostMallocDefault) != hipSuccess) {
-        (void)hipFree(b->dev);
+        dev_free(a, custom, b->dev);
         delete b;
         return nullptr;
     }
     if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
-        (void)hipFree(b->dev);
+        dev_free(a, custom, b->dev);
         (void)hipHostFree(b->host);
         delete b;
         return nullptr;
     }
     g_pool.push_back(b);
     return b;
+}
+
+// Host stop words (colt_stop_set): pinned, device-mapped, coherent memory the
+// transport kernel polls.
+std::mutex g_stop_mu;
+int *g_stop_words = nullptr;
+
+int *stop_words()
+{
+    std::lock_guard<std::mutex> lk(g_stop_mu);
+    if (!g_stop_words) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, kStopTokens * sizeof(int),
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+            return nullptr;
+        std::memset(p, 0, kStopTokens * sizeof(int));
+        g_stop_words = (int *)p;
+    }
+    return g_stop_words;
 }
 
 int cu_count()
@@ -193,6 +242,24 @@ int cu_count()
 }
 
 bool finite_pos(double v) { return std::isfinite(v); }
+
+// Lanes a launch may keep resident on this device.
+uint64_t resident_lanes() { return (uint64_t)cu_count() * kMaxLanesPerCU; }
+
+// Slots per sub-buffer of a camera job's march-task buffer: `req` slots in
+// all (0: four times what the lanes of a full launch can still add after a
+// stop request -- two events of n_cams marches each, in chunks -- at least
+// 2^20 and at most 2^26), rounded to whole chunks.
+uint64_t task_sub_slots(uint64_t n_photons, int n_cams, uint64_t req)
+{
+    if (req == 0) {
+        const uint64_t lanes = std::min<uint64_t>(std::max<uint64_t>(n_photons, 64), resident_lanes());
+        const uint64_t per_lane = ((2 * (uint64_t)n_cams + kTaskChunk - 1) / kTaskChunk + 1) * kTaskChunk;
+        req = std::min<uint64_t>(std::max<uint64_t>(4 * lanes * per_lane, 1ull << 20), 1ull << 26);
+    }
+    return std::max<uint64_t>((req / kTaskSubs + kTaskChunk - 1) / kTaskChunk * kTaskChunk,
+                              (uint64_t)kTaskChunk);
+}
 
 }  // namespace
 
@@ -213,9 +280,12 @@ struct colt_grid_s {
 struct colt_graph_s {
     std::vector<colt_job> jobs;
     void *dev = nullptr;
+    colt_allocator alloc{};
+    bool custom = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t quota = 0;
+    bool may_stop = false;
 };
 
 struct colt_job_s {
@@ -223,10 +293,72 @@ struct colt_job_s {
     colt_grid grid = nullptr;
     JobView view{};
     colt_job_params params{};
-    uint64_t launched = 0;
-    hipEvent_t done = nullptr;
-    bool ever_launched = false;
+    // host view of the device cursor: photons reserved by launches so far; it
+    // is exact unless a launch that can stop has run since the last refresh
+    uint64_t h_cursor = 0;
+    uint64_t h_susp = 0;             // suspended photons at the last refresh
+    bool uncertain = false;          // a launch that may have stopped is pending
+    // one event per stream the job's launches ran on (tally and release wait
+    // on all of them)
+    std::vector<std::pair<hipStream_t, hipEvent_t>> ev;
 };
+
+namespace {
+
+hipError_t job_event(colt_job j, hipStream_t s, hipEvent_t *out)
+{
+    for (auto &e : j->ev)
+        if (e.first == s) { *out = e.second; return hipSuccess; }
+    hipEvent_t e = nullptr;
+    const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    if (r != hipSuccess) return r;
+    j->ev.emplace_back(s, e);
+    *out = e;
+    return hipSuccess;
+}
+
+hipError_t job_wait(colt_job j)
+{
+    for (auto &e : j->ev) {
+        const hipError_t r = hipEventSynchronize(e.second);
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+}
+
+// hipSuccess when every launch of the job has ended, hipErrorNotReady if not.
+hipError_t job_query(colt_job j)
+{
+    for (auto &e : j->ev) {
+        const hipError_t r = hipEventQuery(e.second);
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+}
+
+// Waits for the job's launches and reads its device cursor and suspended count.
+hipError_t job_refresh(colt_job j)
+{
+    hipError_t r = job_wait(j);
+    if (r != hipSuccess) return r;
+    JobCtl c;
+    r = hipMemcpy(&c, j->view.ctl, sizeof(JobCtl), hipMemcpyDeviceToHost);
+    if (r != hipSuccess) return r;
+    j->h_cursor = c.cursor;
+    j->h_susp = c.n_in;
+    j->uncertain = false;
+    return hipSuccess;
+}
+
+// Photons a launch of the job may hand out (exact when not uncertain).
+uint64_t job_work_bound(colt_job j, uint64_t quota)
+{
+    const uint64_t left = j->params.n_photons - std::min(j->h_cursor, j->params.n_photons);
+    const uint64_t take = (quota && quota < left) ? quota : left;
+    return take + (j->uncertain ? (uint64_t)j->view.susp_cap : j->h_susp);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -464,17 +596,19 @@ colt_status colt_grid_nonlocal(colt_grid g, double f_nl, void *stream)
                                               it.lo[2] + ((oc & 4) ? h : 0.0)}, h});
                     }
                 }
-        HIP_TRY(hipMalloc(&boxes, hb.size() * sizeof(double)));
-        hipError_t e = hipMemcpy(boxes, hb.data(), hb.size() * sizeof(double),
-                                 hipMemcpyHostToDevice);
+        boxes = (double *)dev_alloc(g->mem.alloc, g->mem.custom, hb.size() * sizeof(double));
+        if (!boxes) return fail(COLT_ERR_NOMEM, "leaf boxes allocation failed");
+        hipError_t e = hipMemcpyAsync(boxes, hb.data(), hb.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
-            (void)hipFree(boxes);
+            dev_free(g->mem.alloc, g->mem.custom, boxes);
             return fail(COLT_ERR_HIP, "leaf boxes upload: %s", hipGetErrorString(e));
         }
     }
     hipError_t e = launch_nonlocal(g->view, g->n_dev, boxes, nl, f_nl, g->aux_d, g->aux_f, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (boxes) (void)hipFree(boxes);
+    dev_free(g->mem.alloc, g->mem.custom, boxes);
     if (e != hipSuccess) return fail(COLT_ERR_HIP, "non-local estimate: %s", hipGetErrorString(e));
     return COLT_OK;
 }
@@ -501,7 +635,7 @@ colt_status colt_grid_fields(colt_grid g, double *out)
     HIP_TRY(hipMemcpy(rec.data(), g->rec_d, n * sizeof(CellRec<double>), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(aux.data(), g->aux_d, n * sizeof(CellAux<double>), hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < n; ++i) {
-        double *o = out + 10 * i;
+        double *o = out + 11 * i;
         o[0] = rec[i].k0 / g->dx_cm;
         o[1] = rec[i].a;
         o[2] = kVthRef / rec[i].s;
@@ -510,6 +644,7 @@ colt_status colt_grid_fields(colt_grid g, double *out)
         o[7] = rec[i].xcw;
         o[8] = aux[i].g;
         o[9] = aux[i].atau_nl;
+        o[10] = aux[i].atau_j;
     }
     return COLT_OK;
 }
@@ -521,7 +656,7 @@ colt_status colt_emit(colt_grid g, const colt_source_desc *src, const colt_job_p
     *out = nullptr;
     if (p->precision != COLT_FP64 && p->precision != COLT_FP32_BULK)
         return fail(COLT_ERR_ARG, "precision must be COLT_FP64 or COLT_FP32_BULK");
-    if (p->xcrit_mode < 0 || p->xcrit_mode > 2) return fail(COLT_ERR_ARG, "xcrit_mode 0..2");
+    if (p->xcrit_mode < 0 || p->xcrit_mode > 3) return fail(COLT_ERR_ARG, "xcrit_mode 0..3");
     if (p->xcrit_mode == 1 && !(p->atau0 >= 0.0)) return fail(COLT_ERR_ARG, "atau0 must be >= 0");
     if (p->n_bins < 0 || (p->n_bins > 0 && !(p->x_max > p->x_min)))
         return fail(COLT_ERR_ARG, "spectrum needs n_bins >= 0 and x_max > x_min");
@@ -539,6 +674,7 @@ colt_status colt_emit(colt_grid g, const colt_source_desc *src, const colt_job_p
     if (src->kind != 2 && src->n_src != 1) return fail(COLT_ERR_ARG, "kinds 0, 1 take one source");
     if (src->kind == 1 && !(src->sigma >= 0.0)) return fail(COLT_ERR_ARG, "sigma must be >= 0");
     if (src->freq_mode != 0 && src->freq_mode != 1) return fail(COLT_ERR_ARG, "freq_mode 0 or 1");
+    if (p->march_tasks > (1ull << 28)) return fail(COLT_ERR_ARG, "march_tasks above 2^28");
 
     colt_job j = new colt_job_s();
     j->grid = g;
@@ -634,6 +770,39 @@ colt_status colt_emit(colt_grid g, const colt_source_desc *src, const colt_job_p
         v.rec_peel = (double *)m.get(std::max<size_t>(n1 * nc, 1) * sizeof(double));
         ok = v.rec_x && v.rec_nscat && v.rec_status && v.rec_pos && v.rec_peel;
     }
+    // control block and the two suspend arrays (a job's suspended photons
+    // never outnumber the lanes a launch keeps resident)
+    v.susp_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(N, resident_lanes()));
+    if (ok) {
+        v.ctl = (JobCtl *)m.get(sizeof(JobCtl));
+        v.susp[0] = (SuspRec *)m.get((size_t)v.susp_cap * sizeof(SuspRec));
+        v.susp[1] = (SuspRec *)m.get((size_t)v.susp_cap * sizeof(SuspRec));
+        ok = v.ctl && v.susp[0] && v.susp[1];
+    }
+    // march tasks of the next-event estimator: by default four times what the
+    // lanes of a full launch can still add after a stop request (two events of
+    // n_cams marches each, in chunks), at least 2^20 and at most 2^26 slots
+    if (ok && nc > 0) {
+        const uint64_t sub = task_sub_slots(N, nc, p->march_tasks);
+        v.task_sub_cap = (uint32_t)sub;
+        const size_t nt = sub * kTaskSubs;
+        const size_t rb = (p->precision == COLT_FP64) ? 8 : 4;
+        TaskSoA &T = v.task;
+        T.rx = (double *)m.get(nt * 8);
+        T.ry = (double *)m.get(nt * 8);
+        T.rz = (double *)m.get(nt * 8);
+        T.lox = (float *)m.get(nt * 4);
+        T.loy = (float *)m.get(nt * 4);
+        T.loz = (float *)m.get(nt * 4);
+        T.size = (float *)m.get(nt * 4);
+        T.cell = (int32_t *)m.get(nt * 4);
+        T.cam = (int32_t *)m.get(nt * 4);
+        T.xl = m.get(nt * rb);
+        T.W = m.get(nt * rb);
+        T.id = (unsigned long long *)m.get(nt * 8);
+        ok = T.rx && T.ry && T.rz && T.lox && T.loy && T.loz && T.size && T.cell && T.cam &&
+             T.xl && T.W && T.id;
+    }
     if (!ok) {
         m.release_all();
         delete j;
@@ -655,7 +824,7 @@ colt_status colt_emit(colt_grid g, const colt_source_desc *src, const colt_job_p
     if (e == hipSuccess) e = hipMemsetAsync(v.counters, 0, kCounterSlots * kNumCounters * 8, s);
     if (e == hipSuccess && p->record)
         e = hipMemsetAsync(v.rec_peel, 0, std::max<size_t>(std::max<uint64_t>(N, 1) * nc, 1) * 8, s);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&j->done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemsetAsync(v.ctl, 0, sizeof(JobCtl), s);
     // host tables must outlive the asynchronous copies
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -670,22 +839,81 @@ colt_status colt_emit(colt_grid g, const colt_source_desc *src, const colt_job_p
 
 size_t colt_job_bytes(colt_job j) { return j ? j->mem.bytes : 0; }
 
+size_t colt_job_footprint(const colt_job_params *p, int32_t n_src)
+{
+    if (!p || n_src < 1) return 0;
+    auto up = [](size_t n) { return std::max<size_t>((n + 255) & ~size_t(255), 256); };
+    const uint64_t N = p->n_photons;
+    const size_t nc = (size_t)std::max(p->n_cams, 0);
+    size_t b = up(24 * (size_t)n_src) + up(8 * (size_t)n_src) + up(96 * std::max<size_t>(nc, 1));
+    b += up(8 * ((size_t)std::max(p->n_bins, 0) + 2));
+    b += up(8 * std::max<size_t>(nc * std::max(p->cam_nbins, 0), 1));
+    b += up(8 * std::max<size_t>(nc * std::max(p->cam_npix, 0) * std::max(p->cam_npix, 0), 1));
+    b += up(8 * kCounterSlots * kNumCounters);
+    if (p->record) {
+        const size_t n1 = std::max<uint64_t>(N, 1);
+        b += up(8 * n1) + 2 * up(4 * n1) + up(24 * n1) + up(8 * std::max<size_t>(n1 * nc, 1));
+    }
+    const size_t cap = (size_t)std::max<uint64_t>(1, std::min<uint64_t>(N, resident_lanes()));
+    b += up(sizeof(JobCtl)) + 2 * up(cap * sizeof(SuspRec));
+    if (nc > 0) {
+        const size_t nt = task_sub_slots(N, (int)nc, p->march_tasks) * kTaskSubs;
+        const size_t rb = (p->precision == COLT_FP64) ? 8 : 4;
+        b += 4 * up(nt * 8) + 6 * up(nt * 4) + 2 * up(nt * rb);
+    }
+    return b;
+}
+
 colt_status colt_job_status(colt_job j, uint64_t *launched, uint64_t *total)
 {
     if (!j) return fail(COLT_ERR_ARG, "null job");
-    if (launched) *launched = j->launched;
+    if (j->uncertain) {
+        const hipError_t e = job_refresh(j);
+        if (e != hipSuccess) return fail(COLT_ERR_HIP, "job status: %s", hipGetErrorString(e));
+    }
+    if (launched) *launched = j->h_cursor - j->h_susp;
     if (total) *total = j->params.n_photons;
+    return COLT_OK;
+}
+
+colt_status colt_job_pending(colt_job j, uint64_t *next_id, uint64_t *n_suspended,
+                             uint64_t *ids, uint64_t ids_cap)
+{
+    if (!j) return fail(COLT_ERR_ARG, "null job");
+    const hipError_t e = job_refresh(j);
+    if (e != hipSuccess) return fail(COLT_ERR_HIP, "job progress: %s", hipGetErrorString(e));
+    if (next_id) *next_id = j->h_cursor;
+    if (n_suspended) *n_suspended = j->h_susp;
+    const uint64_t n = std::min<uint64_t>(j->h_susp, ids ? ids_cap : 0);
+    if (n) {
+        JobCtl c;
+        HIP_TRY(hipMemcpy(&c, j->view.ctl, sizeof(JobCtl), hipMemcpyDeviceToHost));
+        std::vector<SuspRec> rec(n);
+        HIP_TRY(hipMemcpy(rec.data(), c.cur ? j->view.susp[1] : j->view.susp[0],
+                          n * sizeof(SuspRec), hipMemcpyDeviceToHost));
+        for (uint64_t i = 0; i < n; ++i) ids[i] = rec[i].id;
+        std::sort(ids, ids + n);
+    }
     return COLT_OK;
 }
 
 void colt_release_job(colt_job j)
 {
     if (!j) return;
-    if (j->ever_launched) (void)hipEventSynchronize(j->done);
-    if (j->done) (void)hipEventDestroy(j->done);
+    (void)job_wait(j);
+    for (auto &e : j->ev) (void)hipEventDestroy(e.second);
     j->mem.release_all();
     if (j->grid) j->grid->jobs.fetch_sub(1);
     delete j;
+}
+
+colt_status colt_stop_set(int32_t token, int32_t value)
+{
+    if (token < 1 || token >= kStopTokens) return fail(COLT_ERR_ARG, "stop token 1..%d", kStopTokens - 1);
+    int *w = stop_words();
+    if (!w) return fail(COLT_ERR_NOMEM, "stop words allocation failed");
+    __atomic_store_n(&w[token], value ? 1 : 0, __ATOMIC_SEQ_CST);
+    return COLT_OK;
 }
 
 static int march_min_of(const colt_launch *launch, int precision)
@@ -695,6 +923,112 @@ static int march_min_of(const colt_launch *launch, int precision)
                       : ((precision == COLT_FP64) ? kDefaultMarchMinFp64 : kDefaultMarchMinFp32);
     return m > 64 ? 64 : m;
 }
+
+namespace {
+
+// Byte offsets of one launch's table in device memory.
+struct TableLayout {
+    size_t jobs, prefix, first, rprefix, peel_work, queue, rqueue, stop, bytes;
+};
+
+TableLayout table_layout(int nj)
+{
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    TableLayout t{};
+    size_t o = 0;
+    t.jobs = o; o += up(sizeof(JobView) * nj);
+    t.prefix = o; o += up(8 * (size_t)(nj + 1));
+    t.first = o; o += up(8 * (size_t)nj);
+    t.rprefix = o; o += up(4 * (size_t)(nj + 1));
+    t.peel_work = o; o += up(8 * (size_t)nj);
+    t.queue = o; o += 256;          // the three words polled or hit by atomics
+    t.rqueue = o; o += 256;         // each have a cache line of their own
+    t.stop = o; o += 256;
+    t.bytes = o;
+    return t;
+}
+
+LaunchView table_view(char *dev, const TableLayout &t, int nj, uint64_t quota, int march_min,
+                      const int *stop_host)
+{
+    LaunchView L{};
+    L.jobs = (JobView *)(dev + t.jobs);
+    L.prefix = (uint64_t *)(dev + t.prefix);
+    L.first_id = (uint64_t *)(dev + t.first);
+    L.rprefix = (uint32_t *)(dev + t.rprefix);
+    L.peel_work = (unsigned long long *)(dev + t.peel_work);
+    L.queue = (unsigned long long *)(dev + t.queue);
+    L.rqueue = (unsigned long long *)(dev + t.rqueue);
+    L.stop_dev = (unsigned int *)(dev + t.stop);
+    L.stop_host = stop_host;
+    L.quota = quota;
+    L.n_jobs = nj;
+    L.march_min = march_min;
+    return L;
+}
+
+// Launch shape of a transport launch over `views` (a host bound on the photons
+// it hands out in `work`): workgroups of `block` lanes, at most the resident
+// limit per CU, no more than the work needs, and few enough lanes that every
+// camera job's task buffer keeps room for what its lanes add after a stop.
+// Sets each camera job's high-water mark for this shape.
+colt_status launch_shape(int prec, bool cams, std::vector<JobView> &views, uint64_t work,
+                         int block, int per_cu, int *grid_out)
+{
+    const int nj = (int)views.size();
+    if (per_cu <= 0) {
+        hipError_t e = transport_occupancy(prec, cams, nj == 1, nj == 1 ? views[0].g.kind : -1,
+                                           block, &per_cu);
+        if (e != hipSuccess) return fail(COLT_ERR_HIP, "occupancy: %s", hipGetErrorString(e));
+        if (per_cu <= 0) per_cu = 1;
+    }
+    uint64_t grid = (uint64_t)cu_count() * per_cu;
+    grid = std::min<uint64_t>(grid, (uint64_t)cu_count() * kMaxLanesPerCU / block);
+    const uint64_t lanes_needed = (work + 63) / 64 * 64;
+    grid = std::min<uint64_t>(grid, (lanes_needed + block - 1) / block);
+    for (const JobView &v : views) {
+        if (!v.task_sub_cap) continue;
+        const uint64_t per_lane = ((2 * (uint64_t)v.n_cams + kTaskChunk - 1) / kTaskChunk + 1) * kTaskChunk;
+        const uint64_t max_lanes = (uint64_t)v.task_sub_cap / 2 * kTaskSubs / per_lane;
+        if (max_lanes < 64) return fail(COLT_ERR_ARG, "march-task buffer too small for one wave");
+        grid = std::min<uint64_t>(grid, std::max<uint64_t>(1, max_lanes / block));
+    }
+    if (grid < 1) grid = 1;
+    const uint64_t lanes = grid * block;
+    for (JobView &v : views) {
+        if (!v.task_sub_cap) continue;
+        const uint64_t per_lane = ((2 * (uint64_t)v.n_cams + kTaskChunk - 1) / kTaskChunk + 1) * kTaskChunk;
+        const uint64_t head = (lanes + kTaskSubs - 1) / kTaskSubs * per_lane;
+        v.task_hw = (uint32_t)(v.task_sub_cap - std::min<uint64_t>(head, v.task_sub_cap));
+    }
+    *grid_out = (int)grid;
+    return COLT_OK;
+}
+
+// The kernels of one launch on stream s: plan, transport, the deferred
+// next-event marches of every camera job, advance.
+hipError_t launch_sequence(int prec, bool cams, const LaunchView &L,
+                           const std::vector<JobView> &views, int grid, int block,
+                           int march_min, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
+{
+    hipError_t e = launch_plan(L, false, s);
+    if (e == hipSuccess && t0) e = hipEventRecord(t0, s);
+    if (e == hipSuccess)
+        e = launch_transport(prec, cams, L, views.size() == 1 ? views[0] : JobView{}, grid, block, s);
+    if (e == hipSuccess && t1) e = hipEventRecord(t1, s);
+    for (size_t j = 0; e == hipSuccess && j < views.size(); ++j) {
+        if (!views[j].task_sub_cap) continue;
+        int per_cu = 0;
+        e = peel_occupancy(prec, views[j].g.kind, &per_cu);
+        if (e == hipSuccess)
+            e = launch_peel(prec, views[j], L.peel_work + j, march_min,
+                            cu_count() * std::max(per_cu, 1), s);
+    }
+    if (e == hipSuccess) e = launch_plan(L, true, s);
+    return e;
+}
+
+}  // namespace
 
 colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
                            void *stream)
@@ -706,6 +1040,16 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
         return fail(COLT_ERR_ARG, "block must be 64, 128, 192 or 256");
     const uint64_t quota = launch ? launch->photons_per_job : 0;
     const bool timed = launch && launch->time_kernel;
+    const int token = launch ? launch->stop_token : 0;
+    if (token < 0 || token >= kStopTokens) return fail(COLT_ERR_ARG, "stop token 0..%d", kStopTokens - 1);
+    const int *stop_host = nullptr;
+    if (token) {
+        int *w = stop_words();
+        if (!w) return fail(COLT_ERR_NOMEM, "stop words allocation failed");
+        int *dw = nullptr;
+        HIP_TRY(hipHostGetDevicePointer((void **)&dw, w, 0));
+        stop_host = dw + token;
+    }
     for (int i = 0; i < n_jobs; ++i) {
         if (!jobs[i]) return fail(COLT_ERR_ARG, "null job %d", i);
         for (int k = 0; k < i; ++k)
@@ -713,73 +1057,60 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
     }
     for (int prec = 0; prec < 2; ++prec) {
         std::vector<JobView> views;
-        std::vector<uint64_t> prefix(1, 0), first;
         std::vector<colt_job> members;
         bool cams = false;
+        uint64_t work = 0;
         for (int i = 0; i < n_jobs; ++i) {
             colt_job j = jobs[i];
             if (j->params.precision != prec) continue;
-            const uint64_t left = j->params.n_photons - j->launched;
-            const uint64_t take = (quota && quota < left) ? quota : left;
-            if (take == 0) continue;
+            const uint64_t w = job_work_bound(j, quota);
+            if (w == 0 && !j->uncertain) continue;
             views.push_back(j->view);
-            cams = cams || j->params.n_cams > 0;
-            first.push_back(j->launched);
-            prefix.push_back(prefix.back() + take);
             members.push_back(j);
+            cams = cams || j->params.n_cams > 0;
+            work += w;
         }
         if (members.empty()) continue;
         const int nj = (int)members.size();
-        const size_t off_prefix = ((sizeof(JobView) * nj) + 255) & ~size_t(255);
-        const size_t off_first = off_prefix + ((8 * (nj + 1) + 255) & ~size_t(255));
-        const size_t off_queue = off_first + ((8 * nj + 255) & ~size_t(255));
-        const size_t bytes = off_queue + 256;
-        LaunchBuf *b = acquire_launch_buf(bytes);
+        const bool may_stop = token != 0 || cams;
+        // a launch that may stop, or a job another such launch may have left
+        // suspended photons to, must follow the job's launches on other streams
+        for (colt_job j : members) {
+            if (!(may_stop || j->uncertain)) continue;
+            for (auto &e : j->ev)
+                if (e.first != s) HIP_TRY(hipStreamWaitEvent(s, e.second, 0));
+        }
+        int grid = 0;
+        const colt_status st = launch_shape(prec, cams, views, work, block,
+                                            launch ? launch->blocks_per_cu : 0, &grid);
+        if (st != COLT_OK) return st;
+        const TableLayout t = table_layout(nj);
+        LaunchBuf *b = acquire_launch_buf(t.bytes, members[0]->mem.alloc, members[0]->mem.custom);
         if (!b) return fail(COLT_ERR_NOMEM, "launch table allocation failed");
-        char *h = (char *)b->host;
-        std::memcpy(h, views.data(), sizeof(JobView) * nj);
-        std::memcpy(h + off_prefix, prefix.data(), 8 * (nj + 1));
-        std::memcpy(h + off_first, first.data(), 8 * nj);
-        std::memset(h + off_queue, 0, 256);
-        HIP_TRY(hipMemcpyAsync(b->dev, b->host, bytes, hipMemcpyHostToDevice, s));
-        LaunchView L{};
-        char *dv = (char *)b->dev;
-        L.jobs = (const JobView *)dv;
-        L.prefix = (const uint64_t *)(dv + off_prefix);
-        L.first_id = (const uint64_t *)(dv + off_first);
-        L.queue = (unsigned long long *)(dv + off_queue);
-        L.n_jobs = nj;
-        L.march_min = march_min_of(launch, prec);
-        const uint64_t total = prefix.back();
-        int per_cu = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 0;
-        if (per_cu <= 0) {
-            HIP_TRY(transport_occupancy(prec, cams, nj == 1, nj == 1 ? views[0].g.kind : -1, block,
-                                        &per_cu));
-            if (per_cu <= 0) per_cu = 1;
+        std::memset(b->host, 0, t.bytes);
+        std::memcpy((char *)b->host + t.jobs, views.data(), sizeof(JobView) * nj);
+        HIP_TRY(hipMemcpyAsync(b->dev, b->host, t.bytes, hipMemcpyHostToDevice, s));
+        const LaunchView L = table_view((char *)b->dev, t, nj, quota, march_min_of(launch, prec),
+                                        stop_host);
+        if (timed && !g_t0) {
+            HIP_TRY(hipEventCreate(&g_t0));
+            HIP_TRY(hipEventCreate(&g_t1));
         }
-        const uint64_t lanes_needed = (total + 63) / 64 * 64;
-        uint64_t grid = (uint64_t)cu_count() * per_cu;
-        const uint64_t grid_needed = (lanes_needed + block - 1) / block;
-        if (grid > grid_needed) grid = grid_needed;
-        if (grid < 1) grid = 1;
-        if (timed) {
-            if (!g_t0) {
-                HIP_TRY(hipEventCreate(&g_t0));
-                HIP_TRY(hipEventCreate(&g_t1));
-            }
-            HIP_TRY(hipEventRecord(g_t0, s));
-        }
-        HIP_TRY(launch_transport(prec, cams, L, nj == 1 ? views[0] : JobView{}, (int)grid, block, s));
-        if (timed) {
-            HIP_TRY(hipEventRecord(g_t1, s));
-            g_timed = true;
-        }
+        HIP_TRY(launch_sequence(prec, cams, L, views, grid, block, L.march_min, s,
+                                timed ? g_t0 : nullptr, timed ? g_t1 : nullptr));
+        if (timed) g_timed = true;
         HIP_TRY(hipEventRecord(b->done, s));
-        for (int i = 0; i < nj; ++i) {
-            colt_job j = members[i];
-            j->launched += prefix[i + 1] - prefix[i];
-            HIP_TRY(hipEventRecord(j->done, s));
-            j->ever_launched = true;
+        for (colt_job j : members) {
+            if (!j->uncertain && !may_stop) {
+                const uint64_t left = j->params.n_photons - j->h_cursor;
+                j->h_cursor += (quota && quota < left) ? quota : left;
+                j->h_susp = 0;
+            } else {
+                j->uncertain = true;
+            }
+            hipEvent_t ev = nullptr;
+            HIP_TRY(job_event(j, s, &ev));
+            HIP_TRY(hipEventRecord(ev, s));
         }
     }
     return COLT_OK;
@@ -794,6 +1125,7 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
     if (!capture_stream) return fail(COLT_ERR_ARG, "capture needs a non-default stream");
     const int prec = jobs[0] ? jobs[0]->params.precision : 0;
     bool cams = false;
+    std::vector<JobView> views;
     for (int i = 0; i < n_jobs; ++i) {
         if (!jobs[i]) return fail(COLT_ERR_ARG, "null job %d", i);
         if (jobs[i]->params.precision != prec)
@@ -801,61 +1133,49 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
         for (int k = 0; k < i; ++k)
             if (jobs[k] == jobs[i]) return fail(COLT_ERR_ARG, "job %d listed twice", i);
         cams = cams || jobs[i]->params.n_cams > 0;
+        views.push_back(jobs[i]->view);
     }
     const int block = (launch && launch->block) ? launch->block : 256;
     if (block < 64 || block > 256 || block % 64) return fail(COLT_ERR_ARG, "block 64..256");
-    int per_cu = (launch && launch->blocks_per_cu) ? launch->blocks_per_cu : 0;
-    if (per_cu <= 0) {
-        HIP_TRY(transport_occupancy(prec, cams, n_jobs == 1,
-                                    n_jobs == 1 ? jobs[0]->view.g.kind : -1, block, &per_cu));
-        if (per_cu <= 0) per_cu = 1;
+    const int token = launch ? launch->stop_token : 0;
+    if (token < 0 || token >= kStopTokens) return fail(COLT_ERR_ARG, "stop token 0..%d", kStopTokens - 1);
+    const int *stop_host = nullptr;
+    if (token) {
+        int *w = stop_words();
+        if (!w) return fail(COLT_ERR_NOMEM, "stop words allocation failed");
+        int *dw = nullptr;
+        HIP_TRY(hipHostGetDevicePointer((void **)&dw, w, 0));
+        stop_host = dw + token;
     }
     const int nj = n_jobs;
-    const size_t off_n = ((sizeof(JobView) * nj) + 255) & ~size_t(255);
-    const size_t off_cur = off_n + ((8 * nj + 255) & ~size_t(255));
-    const size_t off_prefix = off_cur + ((8 * nj + 255) & ~size_t(255));
-    const size_t off_first = off_prefix + ((8 * (nj + 1) + 255) & ~size_t(255));
-    const size_t off_queue = off_first + ((8 * nj + 255) & ~size_t(255));
-    const size_t bytes = off_queue + 256;
-    std::vector<char> h(bytes, 0);
-    for (int i = 0; i < nj; ++i) {
-        std::memcpy(h.data() + i * sizeof(JobView), &jobs[i]->view, sizeof(JobView));
-        const uint64_t n = jobs[i]->params.n_photons, c = jobs[i]->launched;
-        std::memcpy(h.data() + off_n + 8 * i, &n, 8);
-        std::memcpy(h.data() + off_cur + 8 * i, &c, 8);
-    }
+    int grid = 0;
+    // a replay's work is not known when it is captured: size for a full device
+    const colt_status st = launch_shape(prec, cams, views, ~0ull >> 8, block,
+                                        launch ? launch->blocks_per_cu : 0, &grid);
+    if (st != COLT_OK) return st;
+    const TableLayout t = table_layout(nj);
+    std::vector<char> h(t.bytes, 0);
+    std::memcpy(h.data() + t.jobs, views.data(), sizeof(JobView) * nj);
     colt_graph gr = new colt_graph_s();
     gr->jobs.assign(jobs, jobs + nj);
     gr->quota = launch ? launch->photons_per_job : 0;
-    if (hipMalloc(&gr->dev, bytes) != hipSuccess) {
+    gr->may_stop = token != 0 || cams;
+    gr->alloc = jobs[0]->mem.alloc;
+    gr->custom = jobs[0]->mem.custom;
+    gr->dev = dev_alloc(gr->alloc, gr->custom, t.bytes);
+    if (!gr->dev) {
         delete gr;
         return fail(COLT_ERR_NOMEM, "graph tables allocation failed");
     }
     hipStream_t s = (hipStream_t)capture_stream;
-    hipError_t e = hipMemcpy(gr->dev, h.data(), bytes, hipMemcpyHostToDevice);
-    char *dv = (char *)gr->dev;
-    PlanView P{};
-    P.n_jobs = nj;
-    P.quota = gr->quota;
-    P.n_photons = (const uint64_t *)(dv + off_n);
-    P.cursor = (uint64_t *)(dv + off_cur);
-    P.prefix = (uint64_t *)(dv + off_prefix);
-    P.first_id = (uint64_t *)(dv + off_first);
-    P.queue = (unsigned long long *)(dv + off_queue);
-    LaunchView L{};
-    L.march_min = march_min_of(launch, prec);
-    L.jobs = (const JobView *)dv;
-    L.prefix = P.prefix;
-    L.first_id = P.first_id;
-    L.queue = P.queue;
-    L.n_jobs = nj;
-    const int grid = cu_count() * per_cu;
+    hipError_t e = hipMemcpyAsync(gr->dev, h.data(), t.bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const LaunchView L = table_view((char *)gr->dev, t, nj, gr->quota, march_min_of(launch, prec),
+                                    stop_host);
     if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = launch_plan(P, false, s);
-        if (e1 == hipSuccess)
-            e1 = launch_transport(prec, cams, L, nj == 1 ? jobs[0]->view : JobView{}, grid, block, s);
-        if (e1 == hipSuccess) e1 = launch_plan(P, true, s);
+        const hipError_t e1 = launch_sequence(prec, cams, L, views, grid, block, L.march_min, s,
+                                              nullptr, nullptr);
         e = hipStreamEndCapture(s, &gr->graph);
         if (e1 != hipSuccess) e = e1;
     }
@@ -863,7 +1183,7 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
     if (e != hipSuccess) {
         if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
         if (gr->graph) (void)hipGraphDestroy(gr->graph);
-        (void)hipFree(gr->dev);
+        dev_free(gr->alloc, gr->custom, gr->dev);
         delete gr;
         return fail(COLT_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
     }
@@ -875,12 +1195,23 @@ colt_status colt_graph_launch(colt_graph gr, void *stream)
 {
     if (!gr) return fail(COLT_ERR_ARG, "null graph");
     hipStream_t s = (hipStream_t)stream;
+    for (colt_job j : gr->jobs) {
+        if (!(gr->may_stop || j->uncertain)) continue;
+        for (auto &e : j->ev)
+            if (e.first != s) HIP_TRY(hipStreamWaitEvent(s, e.second, 0));
+    }
     HIP_TRY(hipGraphLaunch(gr->exec, s));
     for (colt_job j : gr->jobs) {        // host mirror of the device plan
-        const uint64_t left = j->params.n_photons - j->launched;
-        j->launched += (gr->quota && gr->quota < left) ? gr->quota : left;
-        HIP_TRY(hipEventRecord(j->done, s));
-        j->ever_launched = true;
+        if (!j->uncertain && !gr->may_stop) {
+            const uint64_t left = j->params.n_photons - j->h_cursor;
+            j->h_cursor += (gr->quota && gr->quota < left) ? gr->quota : left;
+            j->h_susp = 0;
+        } else {
+            j->uncertain = true;
+        }
+        hipEvent_t ev = nullptr;
+        HIP_TRY(job_event(j, s, &ev));
+        HIP_TRY(hipEventRecord(ev, s));
     }
     return COLT_OK;
 }
@@ -891,7 +1222,7 @@ void colt_graph_release(colt_graph gr)
     if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
     if (gr->graph) (void)hipGraphDestroy(gr->graph);
     (void)hipDeviceSynchronize();
-    (void)hipFree(gr->dev);
+    dev_free(gr->alloc, gr->custom, gr->dev);
     delete gr;
 }
 
@@ -907,16 +1238,21 @@ double colt_last_kernel_ms(void)
 colt_status colt_tally(colt_job j, colt_tally_out *o, int32_t wait)
 {
     if (!j || !o) return fail(COLT_ERR_ARG, "null job or output");
-    if (j->ever_launched) {
-        if (wait) {
-            HIP_TRY(hipEventSynchronize(j->done));
-        } else {
-            hipError_t q = hipEventQuery(j->done);
-            if (q == hipErrorNotReady) return fail(COLT_ERR_BUSY, "job still running");
-            if (q != hipSuccess) return fail(COLT_ERR_HIP, "event query: %s", hipGetErrorString(q));
-        }
+    if (wait) {
+        const hipError_t e = job_wait(j);
+        if (e != hipSuccess) return fail(COLT_ERR_HIP, "job wait: %s", hipGetErrorString(e));
     } else {
-        HIP_TRY(hipStreamSynchronize(j->grid->stream));
+        const hipError_t q = job_query(j);
+        if (q == hipErrorNotReady) return fail(COLT_ERR_BUSY, "job still running");
+        if (q != hipSuccess) return fail(COLT_ERR_HIP, "event query: %s", hipGetErrorString(q));
+    }
+    HIP_TRY(hipStreamSynchronize(j->grid->stream));
+    {
+        JobCtl c;
+        HIP_TRY(hipMemcpy(&c, j->view.ctl, sizeof(JobCtl), hipMemcpyDeviceToHost));
+        if (c.overflow)
+            return fail(COLT_ERR_STATE, "%u suspended photons or next-event marches found no "
+                        "room (results incomplete)", c.overflow);
     }
     const colt_job_params &p = j->params;
     const JobView &v = j->view;

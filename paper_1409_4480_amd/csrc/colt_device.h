@@ -118,6 +118,16 @@ struct Rng<double> {
         k = (k + 1) & ~(uint64_t)1;
         return k >> 1;
     }
+    // continues the stream at draw index k0 (a suspended photon): the words of
+    // a partly used block are recomputed
+    __device__ __forceinline__ void restore(uint64_t k0)
+    {
+        k = k0;
+        if (k & 1) {
+            uint32_t lo, hi;
+            key.block(k >> 1, lo, hi, w2, w3);
+        }
+    }
 };
 
 template <>
@@ -168,6 +178,20 @@ struct Rng<float> {
     {
         k = (k + 3) & ~(uint64_t)3;
         return k >> 2;
+    }
+    // continues the stream at draw index k0: at position m = k0 mod 4 of a
+    // block the cache holds its words m, m+1, m+2 (those that exist)
+    __device__ __forceinline__ void restore(uint64_t k0)
+    {
+        k = k0;
+        const uint32_t m = (uint32_t)k & 3u;
+        if (m) {
+            uint32_t w[4];
+            key.block(k >> 2, w[0], w[1], w[2], w[3]);
+            w1 = (m == 1) ? w[1] : ((m == 2) ? w[2] : w[3]);
+            w2 = (m == 1) ? w[2] : w[3];
+            w3 = w[3];
+        }
     }
 };
 

@@ -12,6 +12,15 @@ constexpr double kVthRef = 12.85;          // km/s, thermal speed at 1e4 K (Sec.
 constexpr int kCounterSlots = 64;          // counter copies per job (spread atomics)
 constexpr int kNumCounters = 16;
 constexpr int kMaxCams = 64;
+// Lanes per CU a transport launch may keep resident (the grid is clamped to
+// it); it bounds the photons in flight, hence a job's suspended photons.
+constexpr int kMaxLanesPerCU = 1024;
+// Sub-buffers of a camera job's march-task buffer (spread append atomics).
+constexpr int kTaskSubs = 32;
+// Slots a lane reserves in a task sub-buffer at a time.
+constexpr int kTaskChunk = 8;
+// Host stop words (colt_stop_set tokens 1 .. kStopTokens-1).
+constexpr int kStopTokens = 64;
 // Lanes in flight that keep a wave ray tracing (measured best on the 64^3
 // dusty sphere: 16 of 64 lanes).
 constexpr int kDefaultMarchMinFp32 = 16;
@@ -26,10 +35,50 @@ struct alignas(8 * sizeof(R)) CellRec {
     R ux, uy, uz, xcw;
 };
 
-// Data only needed at scattering events: recoil parameter, non-local a*tau.
+// Data only needed at scattering events: recoil parameter, non-local a*tau,
+// Jeans a*tau.
 template <typename R>
-struct alignas(2 * sizeof(R)) CellAux {
-    R g, atau_nl;
+struct alignas(4 * sizeof(R)) CellAux {
+    R g, atau_nl, atau_j, pad;
+};
+
+// A photon between launches: its state at a pass boundary of the wave loop,
+// where every live photon is in flight with its optical depth to go (128 B).
+// The direction and frequency are kept in double for both precisions (FP32
+// values convert exactly); the generator's cached words are recomputed from
+// the draw index.
+struct SuspRec {
+    double r[3];
+    double tau;
+    double lo[3];
+    double size;
+    double k[3];
+    double x;
+    unsigned long long events, id, rng_k;
+    int32_t cell, nscat;
+};
+static_assert(sizeof(SuspRec) == 128, "suspended photon record is one 128-byte line");
+
+// Per-job control block in device memory.
+struct JobCtl {
+    unsigned long long cursor;      // next photon id not yet handed to a launch
+    unsigned int n_in;              // suspended photons to resume, in susp[cur]
+    unsigned int n_out;             // suspended by the running launch, in susp[cur ^ 1]
+    unsigned int cur;
+    unsigned int overflow;          // photons or march tasks that found no room (error)
+    unsigned int pad[10];
+    unsigned int tn[kTaskSubs * 16];   // march-task slots reserved per sub-buffer (64 B apart)
+};
+
+// Deferred next-event marches of a camera job, structure of arrays: a march
+// starts at the event's position in the event's cell with zero optical depth.
+// Slots whose cam is -1 are unused.
+struct TaskSoA {
+    double *rx, *ry, *rz;
+    float *lox, *loy, *loz, *size;     // cell box in base-cell units (exact dyadics)
+    int32_t *cell, *cam;
+    void *xl, *W;                      // lab frequency and phase weight (R)
+    unsigned long long *id;
 };
 
 struct GridView {
@@ -74,31 +123,35 @@ struct JobView {
     double *rec_peel;
     double dx_cm;                   // grid unit in cm (for recorded positions)
     double box_min_cm[3];
+    // preemption and deferred marches
+    JobCtl *ctl;
+    SuspRec *susp[2];
+    uint32_t susp_cap;              // records per suspend array
+    uint32_t task_sub_cap;          // slots per task sub-buffer (0: no cameras)
+    uint32_t task_hw;               // reserve beyond this in a sub-buffer: stop the launch
+    uint32_t pad2;
+    TaskSoA task;
 };
 
-// One persistent launch: jobs[j] takes global queue indices
-// [prefix[j], prefix[j+1]) as photon ids first_id[j] + (index - prefix[j]);
-// prefix[n_jobs] is the number of photons of the launch.  The tables live in
-// device memory, so a captured graph can re-plan them on every replay.
+// One persistent launch, planned on the device (k_plan) from the jobs'
+// control blocks: jobs[j] resumes its suspended photons as resume indices
+// [rprefix[j], rprefix[j+1]) and takes new photons as queue indices
+// [prefix[j], prefix[j+1]), ids first_id[j] + (index - prefix[j]).  Resumes
+// are handed out first (rqueue), then new photons (queue).  The tables live in
+// device memory, so a captured graph re-plans them on every replay.
 struct LaunchView {
-    const JobView *jobs;
-    const uint64_t *prefix;
-    const uint64_t *first_id;
-    unsigned long long *queue;
-    int32_t n_jobs;
-    int32_t march_min;          // a wave keeps stepping while this many lanes are in flight
-};
-
-// Device-side planning of a graph replay: each job takes up to `quota`
-// photons from its cursor; the cursors advance after the transport.
-struct PlanView {
-    int32_t n_jobs, pad;
-    uint64_t quota;
-    const uint64_t *n_photons;
-    uint64_t *cursor;
+    JobView *jobs;
     uint64_t *prefix;
     uint64_t *first_id;
+    uint32_t *rprefix;
     unsigned long long *queue;
+    unsigned long long *rqueue;
+    unsigned int *stop_dev;     // set on the device (a task buffer near full)
+    const int *stop_host;       // pinned host word (colt_stop_set), or null
+    unsigned long long *peel_work;  // per job: march tasks handed out by k_peel
+    uint64_t quota;             // new photons per job (0: all that remain)
+    int32_t n_jobs;
+    int32_t march_min;          // a wave keeps stepping while this many lanes are in flight
 };
 
 }  // namespace colt

@@ -4,10 +4,12 @@
 //  k_nonlocal     per-cell non-local a*tau estimate (six axis paths)
 //  k_transport    persistent photon-pool transport: each lane carries one
 //                 photon through emission, cell-by-cell ray tracing,
-//                 scattering and next-event tallies; a lane whose photon has
-//                 escaped or been absorbed takes the next photon from a shared
-//                 queue (one atomic per wave per refill)
-//  k_plan, k_advance   device-side slicing of jobs for graph replays
+//                 scattering and the event-cell part of its next-event
+//                 estimates; a lane whose photon has escaped or been absorbed
+//                 takes the next photon from a shared queue (one atomic per
+//                 wave per refill); a stopped launch suspends its photons
+//  k_peel         persistent next-event marches beyond the event's cell
+//  k_plan, k_advance   device-side slicing of jobs before and after a launch
 //  k_voigt, k_sample   device checks of H(a,x) and of the samplers
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -22,13 +24,20 @@
 #ifndef COLT_FP64_MIN_BLOCKS
 #define COLT_FP64_MIN_BLOCKS 2
 #endif
+#ifndef COLT_FP32_CAM_MIN_BLOCKS
+#define COLT_FP32_CAM_MIN_BLOCKS 3
+#endif
+#ifndef COLT_PEEL_MIN_BLOCKS
+#define COLT_PEEL_MIN_BLOCKS 4
+#endif
 
 namespace colt {
 
 // ---------------------------------------------------------------------------
 // Cell set-up (Sec. 2): T4 = T/1e4, v_th = 12.85 T4^1/2 km/s, a = 4.702e-4
 // T4^-1/2, sigma0 = 5.898e-14 T4^-1/2 cm^2, recoil g = 2.536e-4 T4^-1/2; the
-// core-wing crossover x_cw from its rational fit in ln a (Sec. 3.2.2).
+// core-wing crossover x_cw from its rational fit in ln a (Sec. 3.2.2); the
+// Jeans estimate a tau_J = 6.428e4 T4^-1/2 n^1/2 (Sec. 3.2.4).
 // Opacities are stored per grid unit (dx_cm), velocities in units of v_th.
 // ---------------------------------------------------------------------------
 __global__ void k_cell_setup(int64_t n, const double *__restrict__ n_HI,
@@ -63,6 +72,9 @@ __global__ void k_cell_setup(int64_t n, const double *__restrict__ n_HI,
     CellAux<double> x;
     x.g = g;
     x.atau_nl = atau_nl ? atau_nl[i] : 0.0;
+    // a tau across one Jeans length of the cell's gas (Sec. 3.2.4, eq. atau0J)
+    x.atau_j = 6.428e4 / sq * ::sqrt(n_HI[i]);
+    x.pad = 0.0;
     ad[i] = x;
     CellRec<float> cf;
     cf.k0 = (float)c.k0; cf.a = (float)c.a; cf.s = (float)c.s; cf.kd = (float)c.kd;
@@ -71,6 +83,8 @@ __global__ void k_cell_setup(int64_t n, const double *__restrict__ n_HI,
     CellAux<float> xf;
     xf.g = (float)x.g;
     xf.atau_nl = (float)x.atau_nl;
+    xf.atau_j = (float)x.atau_j;
+    xf.pad = 0.0f;
     af[i] = xf;
 }
 
@@ -409,35 +423,6 @@ __device__ __forceinline__ void isotropic_dir(Photon<R> &p)
     set_dir(p, st * c, st * s, mu);
 }
 
-// Optical depth along camera direction d (inverse id) from r in cell c (whose
-// line data the caller holds in cr0) to the domain edge for lab frequency xl,
-// added to tau0; negative once above the cut-off.
-template <typename R>
-__device__ __forceinline__ double peel_tau(const JobView &J, CellBox c, const CellRec<R> &cr0,
-                                           const double r0[3], const double d[3],
-                                           const double id[3], R xl, const R dr[3],
-                                           double tau0, LaneCounters &lc)
-{
-    double r[3] = {r0[0], r0[1], r0[2]};
-    double tau = tau0;
-    CellRec<R> cr = cr0;
-    for (;;) {
-        int axis;
-        bool by_sphere;
-        const double l = exit_distance(J.g, c, r, d, id, axis, by_sphere);
-        const R xloc = xl * cr.s - (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz);
-        const R kt = cr.k0 * voigt_H<R>(cr.a, xloc) + cr.kd;
-        tau += (double)kt * l;
-        lc.add(C_PEEL_CROSSINGS);
-        if (tau > J.tau_peel_max) return -1.0;
-        if (by_sphere) return tau;
-#pragma unroll
-        for (int e = 0; e < 3; ++e) r[e] += l * d[e];
-        if (!cross(J.g, c, r, d, axis)) return tau;
-        cr = load_cell<R>(J.g, c.cell);
-    }
-}
-
 // What an event contributes toward camera direction d: comoving frequency
 // base + d.ua + g (k.d - 1) and phase weight (1 + rW (k.d)^2) / (1 + rW/3).
 // Emission: base = x_nat, ua = atom velocity; dust: base = x, ua = 0; H I:
@@ -446,33 +431,6 @@ template <typename R>
 struct PeelSource {
     R base, grec, rW;
     R ua[3];
-};
-
-// Deferred peel-off marches.  A camera's march from an event usually ends in
-// the event's own cell (optical depth above the cut-off), which the event's
-// lane settles at once; a march that goes on is posted to its wave's queue in
-// LDS and continued by whichever lanes are free, a step at a time, in later
-// passes -- so one long march to the domain edge does not hold the wave.  The
-// optical depth and the tallies are the same either way.
-constexpr int kPeelSlots = 64;
-
-template <typename R>
-struct PeelTask {
-    double r[3];              // position on the entry face of the current cell
-    double lo[3];             // current cell box
-    double size;
-    double tau;               // optical depth so far
-    R xl, W;                  // lab frequency and phase weight of the contribution
-    int32_t cell, cam, bin, pix, job;
-    uint32_t id0, id1;        // photon id (per-photon records)
-};
-
-template <typename R>
-struct PeelQueue {
-    PeelTask<R> *slots;       // the wave's kPeelSlots tasks
-    int *count;               // tasks posted; beyond kPeelSlots the lane ran them itself
-    int job;                  // the lane's job index in the launch
-    const double *cams;       // its camera table (an LDS copy in single-job launches)
 };
 
 // W exp(-tau) of camera `cam` into its spectrum bin and image pixel (and the
@@ -486,134 +444,145 @@ __device__ __forceinline__ void peel_tally(const JobView &J, int cam, int bin, i
     if (pix >= 0) atomicAdd(J.cam_img + (size_t)cam * J.npix * J.npix + pix, w);
 }
 
-// One step of a deferred march: the optical depth of the task's current cell.
-// Returns 0 when it goes on in the next cell, 1 at the domain edge (tally), 2
-// above the cut-off (no contribution).
-template <typename R>
-__device__ __forceinline__ int peel_step(const JobView &J, const double *cams, PeelTask<R> &t,
-                                         LaneCounters &lc)
+// Image pixel of position r (grid units) for camera table entry cam:
+// orthographic projection onto the camera's (u, v) axes about the box centre.
+__device__ __forceinline__ int pixel_of(const JobView &J, const double *cam, const double r[3])
 {
-    const double *cam = cams + 12 * t.cam;
-    const double d[3] = {cam[0], cam[1], cam[2]};
-    const double id[3] = {cam[3], cam[4], cam[5]};
-    const R dr[3] = {(R)cam[0], (R)cam[1], (R)cam[2]};
-    CellBox c;
-    c.lo[0] = t.lo[0]; c.lo[1] = t.lo[1]; c.lo[2] = t.lo[2];
-    c.size = t.size;
-    c.cell = t.cell;
-    const CellRec<R> cr = load_cell<R>(J.g, c.cell);
-    int axis;
-    bool by_sphere;
-    const double l = exit_distance(J.g, c, t.r, d, id, axis, by_sphere);
-    const R xloc = t.xl * cr.s - (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz);
-    const R kt = cr.k0 * voigt_H<R>(cr.a, xloc) + cr.kd;
-    t.tau += (double)kt * l;
-    lc.add(C_PEEL_CROSSINGS);
-    if (t.tau > J.tau_peel_max) return 2;
-    if (by_sphere) return 1;
+    if (J.npix <= 0) return -1;
+    double pu = 0.0, pv = 0.0;
 #pragma unroll
-    for (int e = 0; e < 3; ++e) t.r[e] += l * d[e];
-    if (!cross(J.g, c, t.r, d, axis)) return 1;
-    t.lo[0] = c.lo[0]; t.lo[1] = c.lo[1]; t.lo[2] = c.lo[2];
-    t.size = c.size;
-    t.cell = c.cell;
-    return 0;
+    for (int e = 0; e < 3; ++e) {
+        const double rc = r[e] - J.g.centre[e];
+        pu += rc * cam[6 + e];
+        pv += rc * cam[9 + e];
+    }
+    pu = pu / J.fov + 0.5;
+    pv = pv / J.fov + 0.5;
+    if (!(pu >= 0.0 && pu < 1.0 && pv >= 0.0 && pv < 1.0)) return -1;
+    int iu = (int)(pu * J.npix), iv = (int)(pv * J.npix);
+    iu = (iu >= J.npix) ? J.npix - 1 : iu;
+    iv = (iv >= J.npix) ? J.npix - 1 : iv;
+    return iv * J.npix + iu;
 }
 
-// One next-event contribution per camera from an event at p.r in cell p.c
-// (Sec. 6.1, eq. SB): W exp(-tau_esc) into the camera spectrum and image.
+// Optical depth of the cell c from r along camera direction d (inverse id)
+// to its exit, for lab frequency xl (the cell's line data in cr); the exit
+// axis and whether it is the escape sphere are returned.
 template <typename R>
-__device__ __forceinline__ void peel_off(const JobView &J, const Photon<R> &p,
-                                         const CellRec<R> &cr, const PeelSource<R> &ps,
-                                         PeelQueue<R> &pq, LaneCounters &lc)
+__device__ __forceinline__ double peel_cell_tau(const JobView &J, const CellBox &c,
+                                                const CellRec<R> &cr, const double r[3],
+                                                const double d[3], const double id[3],
+                                                const R dr[3], R xl, double &l, int &axis,
+                                                bool &by_sphere)
+{
+    l = exit_distance(J.g, c, r, d, id, axis, by_sphere);
+    const R xloc = xl * cr.s - (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz);
+    const R kt = cr.k0 * voigt_H<R>(cr.a, xloc) + cr.kd;
+    return (double)kt * l;
+}
+
+// March-task slots a lane holds: it reserves kTaskChunk consecutive slots of
+// its sub-buffer at a time (slot == end: none held).
+struct TaskCursor {
+    uint32_t slot, end;
+};
+
+// Marks the lane's unused reserved slots as empty (cam = -1).
+__device__ __forceinline__ void close_tasks(const JobView &J, TaskCursor &tc)
+{
+    for (; tc.slot < tc.end; ++tc.slot) J.task.cam[tc.slot] = -1;
+}
+
+// The next-event estimate of one event (Sec. 6.1, eq. SB) for every camera:
+// W(mu_c) and the frequency x_c the photon would have toward the camera, from
+// the event's own atom velocity; then the optical depth across the rest of the
+// event's cell.  Above the cut-off the contribution is nil; a march that leaves
+// the domain through the escape sphere inside the cell is tallied at once; any
+// other march is written as a task (event position, cell, frequency, weight)
+// for the march kernel, which follows it to the domain edge.  A lane whose
+// sub-buffer fills past the high-water mark asks the launch to stop.
+template <typename R>
+__device__ __forceinline__ void peel_event(const JobView &J, const double *cams,
+                                           const Photon<R> &p, const CellRec<R> &cr,
+                                           const PeelSource<R> &ps, const R kin[3],
+                                           TaskCursor &tc, int sub, unsigned int *stop_dev,
+                                           LaneCounters &lc)
 {
     using F = Fn<R>;
     const R wn = R(1) + F::div(ps.rW, R(3));
     for (int i = 0; i < J.n_cams; ++i) {
-        const double *cam = pq.cams + 12 * i;
+        const double *cam = cams + 12 * i;
         const double d[3] = {cam[0], cam[1], cam[2]};
         const double id[3] = {cam[3], cam[4], cam[5]};
         const R dr[3] = {(R)cam[0], (R)cam[1], (R)cam[2]};
-        const R muc = p.kr[0] * dr[0] + p.kr[1] * dr[1] + p.kr[2] * dr[2];
+        const R muc = kin[0] * dr[0] + kin[1] * dr[1] + kin[2] * dr[2];
         const R W = F::div(R(1) + ps.rW * muc * muc, wn);
         const R xc = ps.base + (dr[0] * ps.ua[0] + dr[1] * ps.ua[1] + dr[2] * ps.ua[2]) +
                      ps.grec * (muc - R(1));
         const R xl = F::div(xc + (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz), cr.s);
         lc.add(C_PEELS);
-        // the event's own cell, whose line data are at hand
-        CellBox c = p.c;
-        double r[3] = {p.r[0], p.r[1], p.r[2]};
+        lc.add(C_PEEL_CROSSINGS);
+        double l;
         int axis;
         bool by_sphere;
-        const double l = exit_distance(J.g, c, r, d, id, axis, by_sphere);
-        const R xloc = xl * cr.s - (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz);
-        const R kt = cr.k0 * voigt_H<R>(cr.a, xloc) + cr.kd;
-        double tau = (double)kt * l;
-        lc.add(C_PEEL_CROSSINGS);
+        const double tau = peel_cell_tau<R>(J, p.c, cr, p.r, d, id, dr, xl, l, axis, by_sphere);
         if (tau > J.tau_peel_max) continue;
-        // the contribution may count: its spectrum bin and image pixel
-        const int bin = bin_of((double)xl, J.cam_xmin, J.cam_xmax, J.cam_nbins);
-        int pix = -1;
-        if (J.npix > 0) {
-            double pu = 0.0, pv = 0.0;
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                const double rc = p.r[e] - J.g.centre[e];
-                pu += rc * cam[6 + e];
-                pv += rc * cam[9 + e];
-            }
-            pu = pu / J.fov + 0.5;
-            pv = pv / J.fov + 0.5;
-            if (pu >= 0.0 && pu < 1.0 && pv >= 0.0 && pv < 1.0) {
-                int iu = (int)(pu * J.npix), iv = (int)(pv * J.npix);
-                iu = (iu >= J.npix) ? J.npix - 1 : iu;
-                iv = (iv >= J.npix) ? J.npix - 1 : iv;
-                pix = iv * J.npix + iu;
-            }
+        if (by_sphere) {
+            peel_tally(J, i, bin_of((double)xl, J.cam_xmin, J.cam_xmax, J.cam_nbins),
+                       pixel_of(J, cam, p.r), p.id(), (double)W * ::exp(-tau));
+            continue;
         }
-        bool edge = by_sphere;
-        if (!edge) {
-#pragma unroll
-            for (int e = 0; e < 3; ++e) r[e] += l * d[e];
-            edge = !cross(J.g, c, r, d, axis);
-        }
-        if (!edge) {
-            const int slot = atomicAdd(pq.count, 1);
-            if (slot < kPeelSlots) {
-                PeelTask<R> t;
-#pragma unroll
-                for (int e = 0; e < 3; ++e) {
-                    t.r[e] = r[e];
-                    t.lo[e] = c.lo[e];
-                }
-                t.size = c.size;
-                t.tau = tau;
-                t.xl = xl;
-                t.W = W;
-                t.cell = c.cell;
-                t.cam = i;
-                t.bin = bin;
-                t.pix = pix;
-                t.job = pq.job;
-                t.id0 = p.rng.key.id0;
-                t.id1 = p.rng.key.id1;
-                pq.slots[slot] = t;
+        if (tc.slot == tc.end) {
+            const uint32_t b = atomicAdd(&J.ctl->tn[sub * 16], (unsigned int)kTaskChunk);
+            if (b + kTaskChunk > J.task_hw) atomicOr(stop_dev, 1u);
+            if (b + kTaskChunk > J.task_sub_cap) {
+                // no room: the slots of this reservation that exist stay empty
+                for (uint32_t e = b; e < J.task_sub_cap; ++e)
+                    J.task.cam[(uint32_t)sub * J.task_sub_cap + e] = -1;
+                atomicAdd(&J.ctl->overflow, 1u);
                 continue;
             }
-            // queue full: finish the march here
-            tau = peel_tau<R>(J, c, load_cell<R>(J.g, c.cell), r, d, id, xl, dr, tau, lc);
-            if (tau < 0.0) continue;
+            tc.slot = (uint32_t)sub * J.task_sub_cap + b;
+            tc.end = tc.slot + kTaskChunk;
         }
-        peel_tally(J, i, bin, pix, p.id(), (double)W * ::exp(-tau));
+        const uint32_t t = tc.slot++;
+        const TaskSoA &T = J.task;
+        T.rx[t] = p.r[0];
+        T.ry[t] = p.r[1];
+        T.rz[t] = p.r[2];
+        T.lox[t] = (float)p.c.lo[0];
+        T.loy[t] = (float)p.c.lo[1];
+        T.loz[t] = (float)p.c.lo[2];
+        T.size[t] = (float)p.c.size;
+        T.cell[t] = p.c.cell;
+        T.cam[t] = i;
+        reinterpret_cast<R *>(T.xl)[t] = xl;
+        reinterpret_cast<R *>(T.W)[t] = W;
+        T.id[t] = p.id();
     }
 }
 
 // Emission (Sec. 3.1.1): source position, isotropic direction, frequency,
 // first optical depth; draw order [source][blob offset] mu phi [x_nat, atom
 // velocity] tau.  cr receives the line data of the birth cell.
+// A lane's state for next-event estimates in camera kernels.  An event
+// (emission, dust or H I scattering) leaves its source and the photon's
+// incoming direction here; the estimate itself is made once per pass, at one
+// place in the wave loop, so its code is inlined only once.
+template <typename R>
+struct PeelCtx {
+    const double *cams;       // the job's camera table (an LDS copy in one-job launches)
+    TaskCursor tc;
+    int sub;                  // the lane's task sub-buffer
+    unsigned int *stop_dev;
+    bool pend;                // an event waits for its estimate
+    PeelSource<R> ps;
+    R kin[3];
+};
+
 template <typename R, bool CAMS>
 __device__ __forceinline__ void emit(const JobView &J, Photon<R> &p, uint64_t id,
-                                     CellRec<R> &cr, PeelQueue<R> &pq, LaneCounters &lc)
+                                     CellRec<R> &cr, PeelCtx<R> &pc, LaneCounters &lc)
 {
     using F = Fn<R>;
     p.events = 0;
@@ -673,8 +642,8 @@ __device__ __forceinline__ void emit(const JobView &J, Photon<R> &p, uint64_t id
     p.x = F::div(x + (p.kr[0] * cr.ux + p.kr[1] * cr.uy + p.kr[2] * cr.uz), cr.s);
     if constexpr (CAMS) {
         if (J.n_cams > 0) {
-            const PeelSource<R> ps = {xnat, R(0), R(0), {ua[0], ua[1], ua[2]}};
-            peel_off<R>(J, p, cr, ps, pq, lc);
+            pc.ps = {xnat, R(0), R(0), {ua[0], ua[1], ua[2]}};
+            pc.pend = true;
         }
     }
     p.tau = -(double)F::log(p.rng.next());
@@ -725,8 +694,7 @@ __device__ __forceinline__ int march_step(const JobView &J, Photon<R> &p, CellRe
 // the comoving frequency kept); otherwise an H I scattering (returns true).
 template <typename R, bool CAMS>
 __device__ __forceinline__ bool interact(const JobView &J, Photon<R> &p, const CellRec<R> &cr,
-                                         R xloc, double ktot, PeelQueue<R> &pq,
-                                         LaneCounters &lc)
+                                         R xloc, double ktot, PeelCtx<R> &pc, LaneCounters &lc)
 {
     using F = Fn<R>;
     if (cr.kd > R(0) && p.rng.next() < F::div(cr.kd, (R)ktot)) {
@@ -736,8 +704,8 @@ __device__ __forceinline__ bool interact(const JobView &J, Photon<R> &p, const C
         lc.add(C_SCAT_DUST);
         if constexpr (CAMS) {
             if (J.n_cams > 0) {
-                const PeelSource<R> ps = {xloc, R(0), R(0), {R(0), R(0), R(0)}};
-                peel_off<R>(J, p, cr, ps, pq, lc);
+                pc.ps = {xloc, R(0), R(0), {R(0), R(0), R(0)}};
+                pc.pend = true;
             }
         }
         p.tau = -(double)F::log(p.rng.next());
@@ -753,7 +721,7 @@ __device__ __forceinline__ bool interact(const JobView &J, Photon<R> &p, const C
 template <typename R, bool CAMS>
 __device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
                                                const CellRec<R> &cr, R xloc, R upar,
-                                               PeelQueue<R> &pq, LaneCounters &lc)
+                                               PeelCtx<R> &pc, LaneCounters &lc)
 {
     using F = Fn<R>;
     const R a = cr.a, xcw = cr.xcw;
@@ -764,6 +732,8 @@ __device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
         const CellAux<R> ax = load_aux<R>(J.g, p.c.cell);
         const R atau = a * cr.k0 * (R)min_face_distance(p.c, p.r) + ax.atau_nl;
         xc = xcrit_of<R>(atau);
+    } else if (J.xcrit_mode == 3) {
+        xc = xcrit_of<R>(load_aux<R>(J.g, p.c.cell).atau_j);
     }
     const R axl = (xloc < R(0)) ? -xloc : xloc;
     if (axl >= xcw) xc = R(0);                 // already in the wing: no cut-off
@@ -813,8 +783,11 @@ __device__ __forceinline__ void scatter_finish(const JobView &J, Photon<R> &p,
     lc.add(C_SCAT_HI);
     if constexpr (CAMS) {
         if (J.n_cams > 0) {
-            const PeelSource<R> ps = {xloc - upar, grec, rW, {ua[0], ua[1], ua[2]}};
-            peel_off<R>(J, p, cr, ps, pq, lc);
+            pc.ps = {xloc - upar, grec, rW, {ua[0], ua[1], ua[2]}};
+            pc.kin[0] = p.kr[0];
+            pc.kin[1] = p.kr[1];
+            pc.kin[2] = p.kr[2];
+            pc.pend = true;
         }
     }
     set_dir(p, kf[0], kf[1], kf[2]);
@@ -1051,14 +1024,99 @@ __device__ __forceinline__ int find_job(const LaunchView &L, uint64_t g)
     }
     return lo;
 }
+__device__ __forceinline__ int find_rjob(const LaunchView &L, uint32_t r)
+{
+    int lo = 0, hi = L.n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.rprefix[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
-// Persistent photon pool.  Each pass of the wave loop: idle lanes take new
-// photons from the shared queue (one atomic per wave); the photons in flight
-// take ray-tracing steps, the wave stepping on while at least L.march_min of
-// its lanes are still in flight (the rest resume in the next pass, so one
-// long flight does not hold the whole wave); the wave then serves all
-// parallel-velocity draws cooperatively and completes the scatterings.  A
-// photon's history does not depend on where the passes cut its flights.
+// ---------------------------------------------------------------------------
+// Preemption.  At the end of a pass every live photon is in flight with its
+// optical depth to go, so its whole state fits a SuspRec; a stopped launch
+// writes its photons to the job's other suspend array, and the next launch
+// resumes them (before new photons) with bit-identical continuations.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void suspend(const JobView &J, const Photon<R> &p)
+{
+    const unsigned int cur = J.ctl->cur;
+    const unsigned int i = atomicAdd(&J.ctl->n_out, 1u);
+    if (i >= J.susp_cap) {
+        atomicAdd(&J.ctl->overflow, 1u);
+        return;
+    }
+    SuspRec *s = (cur ? J.susp[0] : J.susp[1]) + i;   // the array not being resumed from
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        s->r[d] = p.r[d];
+        s->lo[d] = p.c.lo[d];
+        s->k[d] = (double)p.kr[d];
+    }
+    s->tau = p.tau;
+    s->size = p.c.size;
+    s->x = (double)p.x;
+    s->events = p.events;
+    s->id = p.id();
+    s->rng_k = p.rng.k;
+    s->cell = p.c.cell;
+    s->nscat = p.nscat;
+}
+
+template <typename R>
+__device__ __forceinline__ void resume(const JobView &J, Photon<R> &p, uint32_t i,
+                                       CellRec<R> &cr)
+{
+    const SuspRec *s = (J.ctl->cur ? J.susp[1] : J.susp[0]) + i;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        p.r[d] = s->r[d];
+        p.c.lo[d] = s->lo[d];
+    }
+    p.c.size = s->size;
+    p.c.cell = s->cell;
+    set_dir(p, (R)s->k[0], (R)s->k[1], (R)s->k[2]);
+    p.x = (R)s->x;
+    p.tau = s->tau;
+    p.events = s->events;
+    p.nscat = s->nscat;
+    p.status = 0;
+    p.rng.init(J.seed, s->id);
+    p.rng.restore(s->rng_k);
+    cr = load_cell<R>(J.g, p.c.cell);
+}
+
+// A stopped launch hands the resumes no lane has taken to the next launch.
+__device__ __forceinline__ void carry_over(const JobView &J, uint32_t i)
+{
+    const unsigned int cur = J.ctl->cur;
+    const unsigned int o = atomicAdd(&J.ctl->n_out, 1u);
+    if (o >= J.susp_cap) {
+        atomicAdd(&J.ctl->overflow, 1u);
+        return;
+    }
+    const SuspRec *in = cur ? J.susp[1] : J.susp[0];
+    SuspRec *out = cur ? J.susp[0] : J.susp[1];
+    out[o] = in[i];
+}
+
+// Host stop words are read every kHostPoll passes (each read crosses PCIe).
+constexpr uint32_t kHostPoll = 32;
+
+// Persistent photon pool.  Each pass of the wave loop: idle lanes take
+// suspended photons to resume, then new photons, from the launch's queues
+// (one atomic per wave for each); the photons in flight take ray-tracing
+// steps, the wave stepping on while at least L.march_min of its lanes are
+// still in flight (the rest resume in the next pass, so one long flight does
+// not hold the whole wave); the wave then serves all parallel-velocity draws
+// cooperatively and completes the scatterings.  At the end of a pass the wave
+// checks for a stop request; a stopped wave suspends its photons and leaves.
+// A photon's history does not depend on where passes cut its flights or on
+// where the launch was stopped.
 // SINGLE launches carry one job.  The FP32 kernels take it by value as J1:
 // its parameters are then kernel arguments, read through the scalar cache
 // (the job table in global memory is re-read with vector loads on every use).
@@ -1068,7 +1126,7 @@ __device__ __forceinline__ int find_job(const LaunchView &L, uint64_t g)
 template <typename R, bool CAMS>
 constexpr int transport_min_blocks()
 {
-    return CAMS ? ((sizeof(R) == 4) ? 2 : 1)
+    return CAMS ? ((sizeof(R) == 4) ? COLT_FP32_CAM_MIN_BLOCKS : 1)
                 : ((sizeof(R) == 4) ? COLT_FP32_MIN_BLOCKS : COLT_FP64_MIN_BLOCKS);
 }
 
@@ -1079,27 +1137,23 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
     __shared__ int32_t s_table[4][64];
     __shared__ uint32_t s_first[4][64];
     __shared__ unsigned long long s_counts[kLaneCounters][kMaxBlock];
-    __shared__ PeelTask<R> s_peel[CAMS ? 4 : 1][CAMS ? kPeelSlots : 1];
-    __shared__ int s_peel_n[4];
+    __shared__ double s_cam[(CAMS && SINGLE) ? 12 * kMaxCams : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + wave) & (kCounterSlots - 1));
-    __shared__ double s_cam[(CAMS && SINGLE) ? 12 * kMaxCams : 1];
-    PeelQueue<R> pq;
-    pq.slots = s_peel[CAMS ? wave : 0];
-    pq.count = &s_peel_n[wave];
-    pq.job = 0;
-    pq.cams = nullptr;
+    PeelCtx<R> pc;
+    pc.pend = false;
+    pc.cams = nullptr;
+    pc.tc.slot = pc.tc.end = 0;
+    pc.sub = (int)((blockIdx.x * blockDim.x + threadIdx.x) & (kTaskSubs - 1));
+    pc.stop_dev = L.stop_dev;
     if constexpr (CAMS && SINGLE) {
-        // the job's camera table, read at every peel-off step, kept in LDS
-        for (int i = threadIdx.x; i < 12 * L.jobs->n_cams; i += blockDim.x)
-            s_cam[i] = L.jobs->cam[i];
-        pq.cams = s_cam;
+        // the job's camera table, read at every next-event estimate, kept in LDS
+        for (int i = threadIdx.x; i < 12 * J1.n_cams; i += blockDim.x) s_cam[i] = J1.cam[i];
+        pc.cams = s_cam;
         __syncthreads();
     }
-    if (lane == 0) s_peel_n[wave] = 0;
-    wave_lds_sync();
     Photon<R> p;
     p.status = 0;
     CellRec<R> cr;                 // line data of the photon's cell while it lives
@@ -1119,46 +1173,93 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
     const JobView *const J_single = (sizeof(R) == 4) ? &Jk : L.jobs;
     const JobView *J = SINGLE ? J_single : nullptr;
     const uint64_t total = L.prefix[L.n_jobs];
+    const uint32_t rtotal = L.rprefix[L.n_jobs];
     const int march_min = L.march_min;
-    bool have = false, moving = false, drained = total == 0;
+    bool res_left = rtotal > 0, new_left = total > 0;
+    bool have = false, moving = false, stopping = false;
+    uint32_t pass = 0;
     for (;;) {
-        if (!drained) {
+        // a stop request set before or during this pass is acted on at its end
+        int stop_word = 0;
+        if (lane == 0) {
+            stop_word = (int)__hip_atomic_load(L.stop_dev, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+            if (L.stop_host && (pass % kHostPoll) == 0)
+                stop_word |= __hip_atomic_load(L.stop_host, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        if (res_left || new_left) {
             const uint64_t need = __ballot(!have);
             if (need) {
                 const int n_need = __popcll(need);
                 const int leader = __ffsll((unsigned long long)need) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(L.queue, (unsigned long long)n_need);
-                const uint32_t blo = __shfl((uint32_t)base, leader);
-                const uint32_t bhi = __shfl((uint32_t)(base >> 32), leader);
-                base = ((unsigned long long)bhi << 32) | blo;
-                if (base + n_need >= total) drained = true;
+                const int rank = __popcll(need & lane_lt);
+                int n_res = 0;
+                uint32_t rbase = 0;
+                if (res_left) {
+                    uint32_t b = 0;
+                    if (lane == leader) b = (uint32_t)atomicAdd(L.rqueue, (unsigned long long)n_need);
+                    b = __shfl(b, leader);
+                    if (b < rtotal) n_res = (rtotal - b < (uint32_t)n_need) ? (int)(rtotal - b) : n_need;
+                    if (b + (uint32_t)n_need >= rtotal) res_left = false;
+                    rbase = b;
+                }
+                unsigned long long qbase = 0;
+                const int n_new = n_need - n_res;
+                bool take_new = false;
+                if (n_new > 0 && new_left) {
+                    if (lane == leader) qbase = atomicAdd(L.queue, (unsigned long long)n_new);
+                    const uint32_t blo = __shfl((uint32_t)qbase, leader);
+                    const uint32_t bhi = __shfl((uint32_t)(qbase >> 32), leader);
+                    qbase = ((unsigned long long)bhi << 32) | blo;
+                    if (qbase + n_new >= total) new_left = false;
+                    take_new = true;
+                }
                 if (!have) {
-                    const uint64_t g = base + __popcll(need & lane_lt);
-                    if (g < total) {
-                        uint64_t id;
-                        if constexpr (SINGLE) {
-                            id = L.first_id[0] + g;
-                        } else {
-                            const int j = find_job(L, g);
-                            const JobView *Jn = &L.jobs[j];
-                            if (Jn != J) {
-                                if (J) flush_counters(J, lc, slot);
-                                J = Jn;
-                            }
+                    int j = -1;
+                    uint64_t id = 0;
+                    uint32_t ri = 0;
+                    const bool res = rank < n_res;
+                    if (res) {
+                        ri = rbase + (uint32_t)rank;
+                        j = SINGLE ? 0 : find_rjob(L, ri);
+                    } else if (take_new) {
+                        const uint64_t g = qbase + (uint64_t)(rank - n_res);
+                        if (g < total) {
+                            j = SINGLE ? 0 : find_job(L, g);
                             id = L.first_id[j] + (g - L.prefix[j]);
                         }
+                    }
+                    if (j >= 0) {
                         if constexpr (!SINGLE) {
-                            pq.job = (int)(J - L.jobs);
-                            pq.cams = J->cam;
+                            const JobView *Jn = &L.jobs[j];
+                            if (Jn != J) {
+                                if (J) {
+                                    flush_counters(J, lc, slot);
+                                    if constexpr (CAMS) close_tasks(*J, pc.tc);
+                                }
+                                J = Jn;
+                                pc.cams = J->cam;
+                            }
                         }
-                        emit<R, CAMS>(*J, p, id, cr, pq, lc);
                         have = true;
                         moving = true;
-                        if (p.status != 0) {
-                            finish<R>(*J, p, lc);
-                            have = false;
-                            moving = false;
+                        if (res) {
+                            resume<R>(*J, p, ri - L.rprefix[j], cr);
+                        } else {
+                            emit<R, CAMS>(*J, p, id, cr, pc, lc);
+                            if (p.status != 0) {
+                                finish<R>(*J, p, lc);
+                                have = false;
+                                moving = false;
+                            } else if (CAMS && pc.pend) {
+                                // the emission's estimate is made this pass,
+                                // from the birth point; the flight starts next
+                                moving = false;
+                                pc.kin[0] = p.kr[0];
+                                pc.kin[1] = p.kr[1];
+                                pc.kin[2] = p.kr[2];
+                            }
                         }
                     }
                 }
@@ -1195,7 +1296,7 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
             q.regime = UPAR_GAUSS;
             uint64_t B0 = 0;
             if (event) {
-                if (interact<R, CAMS>(*J, p, cr, xloc, ktot, pq, lc)) {
+                if (interact<R, CAMS>(*J, p, cr, xloc, ktot, pc, lc)) {
                     hi = true;
                     q = upar_setup<R>(cr.a, xloc, cr.xcw);
                     B0 = p.rng.align();
@@ -1223,7 +1324,15 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
                     if (!ok) p.status = 3;
                 }
                 if (p.status == 0) {
-                    scatter_finish<R, CAMS>(*J, p, cr, xloc, (xloc < R(0)) ? -u : u, pq, lc);
+                    scatter_finish<R, CAMS>(*J, p, cr, xloc, (xloc < R(0)) ? -u : u, pc, lc);
+                    moving = true;
+                }
+            }
+            if constexpr (CAMS) {
+                if (pc.pend) {
+                    peel_event<R>(*J, pc.cams, p, cr, pc.ps, pc.kin, pc.tc, pc.sub, pc.stop_dev,
+                                  lc);
+                    pc.pend = false;
                     moving = true;
                 }
             }
@@ -1233,50 +1342,30 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
                 moving = false;
             }
         }
-        if constexpr (CAMS) {
-            // Deferred peel-off marches: the lanes of the wave take the newest
-            // tasks and step them while a quarter of them (at most march_min)
-            // are still going; the rest wait in the queue.  Once the wave has
-            // no photons left and nothing more to take, it finishes every task
-            // before it leaves.
-            wave_lds_sync();
-            const bool last = drained && !__any(have);
-            int n = *pq.count;
-            n = (n < kPeelSlots) ? n : kPeelSlots;
-            while (n > 0) {
-                const int take = (n < 64) ? n : 64;
-                const int base = n - take;
-                bool act = lane < take;
-                PeelTask<R> t;
-                if (act) t = pq.slots[base + lane];
-                const JobView *Jt = SINGLE ? J_single : &L.jobs[act ? t.job : 0];
-                wave_lds_sync();
-                const int quarter = (take + 3) >> 2;
-                const int stop_below = last ? 1 : ((march_min < quarter) ? march_min : quarter);
-                for (;;) {
-                    if (act) {
-                        const int st = peel_step<R>(*Jt, SINGLE ? s_cam : Jt->cam, t, lc);
-                        if (st != 0) {
-                            act = false;
-                            if (st == 1)
-                                peel_tally(*Jt, t.cam, t.bin, t.pix,
-                                           ((uint64_t)t.id1 << 32) | t.id0,
-                                           (double)t.W * ::exp(-t.tau));
-                        }
-                    }
-                    const int going = __popcll(__ballot(act));
-                    if (going == 0 || going < stop_below) break;
+        ++pass;
+        if (!stopping && __shfl(stop_word, 0) != 0) stopping = true;
+        if (stopping) {
+            if (have) suspend<R>(*J, p);
+            have = false;
+            moving = false;
+            new_left = false;
+            while (res_left) {
+                uint32_t b = 0;
+                if (lane == 0) b = (uint32_t)atomicAdd(L.rqueue, 64ull);
+                b = __shfl(b, 0);
+                if (b + 64u >= rtotal) res_left = false;
+                const uint32_t ri = b + (uint32_t)lane;
+                if (ri < rtotal) {
+                    const int j = SINGLE ? 0 : find_rjob(L, ri);
+                    carry_over(SINGLE ? *J_single : L.jobs[j], ri - L.rprefix[j]);
                 }
-                const uint64_t keep = __ballot(act);
-                if (act) pq.slots[base + __popcll(keep & lane_lt)] = t;
-                n = base + __popcll(keep);
-                wave_lds_sync();
-                if (!last && n <= kPeelSlots / 2) break;
             }
-            if (lane == 0) *pq.count = n;
-            wave_lds_sync();
         }
-        if (!any_have && drained) break;
+        if (!any_have && !res_left && !new_left) break;
+        if (stopping) break;
+    }
+    if constexpr (CAMS) {
+        if (J) close_tasks(*J, pc.tc);
     }
     if constexpr (SINGLE)
         flush_counters_wave(J, lc, slot);
@@ -1285,28 +1374,224 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
 }
 
 // ---------------------------------------------------------------------------
-// Graph replays: plan the next slice of every job from device cursors, and
-// advance the cursors after the transport (no host data in the replay).
+// Launch planning on the device, from the jobs' control blocks, so eager
+// launches and graph replays work the same way and a stopped launch's state is
+// picked up by the next one.  k_plan reserves each job's next slice of new
+// photons (cursor += take, so launches of a job on several streams take
+// disjoint slices) and lays out the resume and new-photon index ranges;
+// k_advance gives back the part of a slice a stopped launch did not reach,
+// swaps the suspend arrays and empties the march-task buffers.  One
+// workgroup of 256 threads each, any number of jobs.
 // ---------------------------------------------------------------------------
-__global__ void k_plan(PlanView P)
+__global__ __launch_bounds__(256) void k_plan(LaunchView L)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint64_t acc = 0;
-    P.prefix[0] = 0;
-    for (int j = 0; j < P.n_jobs; ++j) {
-        const uint64_t left = P.n_photons[j] - P.cursor[j];
-        const uint64_t take = (P.quota && P.quota < left) ? P.quota : left;
-        P.first_id[j] = P.cursor[j];
-        acc += take;
-        P.prefix[j + 1] = acc;
+    __shared__ unsigned long long s_a[256];
+    __shared__ unsigned int s_b[256];
+    const int t = threadIdx.x;
+    unsigned long long carry_a = 0;
+    unsigned int carry_b = 0;
+    for (int base = 0; base < L.n_jobs; base += 256) {
+        const int j = base + t;
+        unsigned long long a = 0;
+        unsigned int b = 0;
+        if (j < L.n_jobs) {
+            // reserve [cursor, cursor + a) atomically: launches of one job on
+            // different streams may plan at the same time
+            JobCtl *c = L.jobs[j].ctl;
+            const unsigned long long n = L.jobs[j].n_photons;
+            unsigned long long cur = __hip_atomic_load(&c->cursor, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            for (;;) {
+                const unsigned long long left = n - cur;
+                a = (L.quota && L.quota < left) ? L.quota : left;
+                const unsigned long long seen = atomicCAS(&c->cursor, cur, cur + a);
+                if (seen == cur) break;
+                cur = seen;
+            }
+            b = c->n_in;
+            L.first_id[j] = cur;
+            c->n_out = 0;
+        }
+        s_a[t] = a;
+        s_b[t] = b;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {          // inclusive scans
+            const unsigned long long ya = (t >= o) ? s_a[t - o] : 0ull;
+            const unsigned int yb = (t >= o) ? s_b[t - o] : 0u;
+            __syncthreads();
+            s_a[t] += ya;
+            s_b[t] += yb;
+            __syncthreads();
+        }
+        if (j < L.n_jobs) {
+            L.prefix[j + 1] = carry_a + s_a[t];
+            L.rprefix[j + 1] = carry_b + s_b[t];
+        }
+        carry_a += s_a[255];
+        carry_b += s_b[255];
+        __syncthreads();
     }
-    *P.queue = 0ull;
+    if (t == 0) {
+        L.prefix[0] = 0;
+        L.rprefix[0] = 0;
+        *L.queue = 0ull;
+        *L.rqueue = 0ull;
+        *L.stop_dev = 0u;
+    }
+    for (int j = t; j < L.n_jobs; j += 256) L.peel_work[j] = 0ull;
 }
 
-__global__ void k_advance(PlanView P)
+__global__ __launch_bounds__(256) void k_advance(LaunchView L)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int j = 0; j < P.n_jobs; ++j) P.cursor[j] += P.prefix[j + 1] - P.prefix[j];
+    const unsigned long long n = L.prefix[L.n_jobs];
+    const unsigned long long q = (*L.queue < n) ? *L.queue : n;
+    for (int j = threadIdx.x; j < L.n_jobs; j += 256) {
+        JobCtl *c = L.jobs[j].ctl;
+        const unsigned long long lo = L.prefix[j], hi = L.prefix[j + 1];
+        const unsigned long long used = (q <= lo) ? 0ull : ((q >= hi) ? hi - lo : q - lo);
+        if (used < hi - lo) atomicAdd(&c->cursor, (unsigned long long)(used - (hi - lo)));
+        if (c->n_in != 0u || c->n_out != 0u) {
+            c->cur ^= 1u;
+            // n_out counts suspension attempts; beyond the array they failed
+            // (and were counted as overflow)
+            c->n_in = (c->n_out < L.jobs[j].susp_cap) ? c->n_out : L.jobs[j].susp_cap;
+            c->n_out = 0u;
+        }
+        if (L.jobs[j].task_sub_cap)
+            for (int b = 0; b < kTaskSubs; ++b) c->tn[b * 16] = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Deferred next-event marches (Sec. 6.1): each task follows one camera's ray
+// from an event to the domain edge, adding the optical depth of every cell
+// (H I at the Doppler-shifted frequency of that cell, and dust), and tallies
+// W exp(-tau) unless the cut-off is passed first.  A lean persistent kernel:
+// lanes take tasks from the job's buffer (one atomic per wave) and step their
+// marches, the wave stepping on while a quarter of its lanes (at most
+// march_min) are still going, so one long march does not hold the wave.  The
+// first step repeats the event cell that the transport kernel already found
+// below the cut-off (it is not counted again).
+// ---------------------------------------------------------------------------
+template <typename R, int GK>
+__global__ __launch_bounds__(256, COLT_PEEL_MIN_BLOCKS) void k_peel(JobView J, unsigned long long *work,
+                                                                  int march_min)
+{
+    __shared__ double s_cam[12 * kMaxCams];
+    __shared__ uint32_t s_pre[kTaskSubs + 1];
+    for (int i = threadIdx.x; i < 12 * J.n_cams; i += blockDim.x) s_cam[i] = J.cam[i];
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b < kTaskSubs; ++b) {
+            s_pre[b] = acc;
+            const uint32_t nb = J.ctl->tn[b * 16];
+            acc += (nb < J.task_sub_cap) ? nb : J.task_sub_cap;
+        }
+        s_pre[kTaskSubs] = acc;
+    }
+    __syncthreads();
+    if constexpr (GK == 0) {
+        J.g.kind = 0;
+        J.g.rope = nullptr;
+    } else if constexpr (GK == 1) {
+        J.g.kind = 1;
+    }
+    const int lane = threadIdx.x & 63;
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t total = s_pre[kTaskSubs];
+    bool drained = total == 0, have = false, first = false;
+    CellBox c;
+    double r[3] = {0.0, 0.0, 0.0}, tau = 0.0;
+    R xl = R(0), W = R(0);
+    int cam = 0, bin = 0, pix = -1;
+    unsigned long long id = 0, steps = 0;
+    for (;;) {
+        if (!drained) {
+            const uint64_t need = __ballot(!have);
+            if (need) {
+                const int n_need = __popcll(need);
+                const int leader = __ffsll((unsigned long long)need) - 1;
+                uint32_t base = 0;
+                if (lane == leader) base = (uint32_t)atomicAdd(work, (unsigned long long)n_need);
+                base = __shfl(base, leader);
+                if (base + (uint32_t)n_need >= total) drained = true;
+                const uint32_t w = base + (uint32_t)__popcll(need & lane_lt);
+                if (!have && w < total) {
+                    int b = 0;
+#pragma unroll
+                    for (int h = kTaskSubs / 2; h > 0; h >>= 1)
+                        if (s_pre[b + h] <= w) b += h;
+                    const uint32_t t = (uint32_t)b * J.task_sub_cap + (w - s_pre[b]);
+                    cam = J.task.cam[t];
+                    if (cam >= 0 && cam < J.n_cams) {
+                        const TaskSoA &T = J.task;
+                        r[0] = T.rx[t];
+                        r[1] = T.ry[t];
+                        r[2] = T.rz[t];
+                        c.lo[0] = (double)T.lox[t];
+                        c.lo[1] = (double)T.loy[t];
+                        c.lo[2] = (double)T.loz[t];
+                        c.size = (double)T.size[t];
+                        c.cell = T.cell[t];
+                        xl = reinterpret_cast<const R *>(T.xl)[t];
+                        W = reinterpret_cast<const R *>(T.W)[t];
+                        id = T.id[t];
+                        bin = bin_of((double)xl, J.cam_xmin, J.cam_xmax, J.cam_nbins);
+                        pix = pixel_of(J, s_cam + 12 * cam, r);
+                        tau = 0.0;
+                        first = true;
+                        have = true;
+                    }
+                }
+            }
+        }
+        if (!__any(have)) {
+            if (drained) break;
+            continue;
+        }
+        const int going0 = __popcll(__ballot(have));
+        const int quarter = (going0 + 3) >> 2;
+        const int stop_below = drained ? 1 : ((march_min < quarter) ? march_min : quarter);
+        for (;;) {
+            if (have) {
+                const double *cm = s_cam + 12 * cam;
+                const double d[3] = {cm[0], cm[1], cm[2]};
+                const double idv[3] = {cm[3], cm[4], cm[5]};
+                const R dr[3] = {(R)cm[0], (R)cm[1], (R)cm[2]};
+                const CellRec<R> cr = load_cell<R>(J.g, c.cell);
+                double l;
+                int axis;
+                bool by_sphere;
+                tau += peel_cell_tau<R>(J, c, cr, r, d, idv, dr, xl, l, axis, by_sphere);
+                if (!first) ++steps;
+                first = false;
+                int st = 0;
+                if (tau > J.tau_peel_max) {
+                    st = 2;
+                } else if (by_sphere) {
+                    st = 1;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) r[e] += l * d[e];
+                    if (!cross(J.g, c, r, d, axis)) st = 1;
+                }
+                if (st) {
+                    have = false;
+                    if (st == 1) peel_tally(J, cam, bin, pix, id, (double)W * ::exp(-tau));
+                }
+            }
+            const int going = __popcll(__ballot(have));
+            if (going == 0 || going < stop_below) break;
+        }
+    }
+    // crossings of the marches beyond the event cell, one atomic per wave
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) steps += __shfl_xor(steps, o);
+    if (lane == 0 && steps) {
+        const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) &
+                               (kCounterSlots - 1));
+        atomicAdd(J.counters + (size_t)slot * kNumCounters + C_PEEL_CROSSINGS, steps);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1519,11 +1804,40 @@ hipError_t transport_occupancy(int precision, bool cams, bool single, int grid_k
                 : occupancy_t<float, false, true, 1>(block, blocks_per_cu);
 }
 
-hipError_t launch_plan(const PlanView &P, bool advance, hipStream_t s)
+hipError_t launch_plan(const LaunchView &L, bool advance, hipStream_t s)
 {
-    if (advance) hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, P);
-    else hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, s, P);
+    if (advance) hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, s, L);
+    else hipLaunchKernelGGL(k_plan, dim3(1), dim3(256), 0, s, L);
     return hipGetLastError();
+}
+
+template <typename R, int GK>
+static hipError_t peel_t(const JobView &J, unsigned long long *work, int march_min, int grid,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL((k_peel<R, GK>), dim3(grid), dim3(256), 0, s, J, work, march_min);
+    return hipGetLastError();
+}
+
+hipError_t launch_peel(int precision, const JobView &J, unsigned long long *work, int march_min,
+                       int grid, hipStream_t s)
+{
+    if (precision == 0)
+        return J.g.kind == 0 ? peel_t<double, 0>(J, work, march_min, grid, s)
+                             : peel_t<double, 1>(J, work, march_min, grid, s);
+    return J.g.kind == 0 ? peel_t<float, 0>(J, work, march_min, grid, s)
+                         : peel_t<float, 1>(J, work, march_min, grid, s);
+}
+
+hipError_t peel_occupancy(int precision, int grid_kind, int *blocks_per_cu)
+{
+    if (precision == 0)
+        return grid_kind == 0
+                   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_peel<double, 0>, 256, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_peel<double, 1>, 256, 0);
+    return grid_kind == 0
+               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_peel<float, 0>, 256, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_peel<float, 1>, 256, 0);
 }
 
 hipError_t launch_nonlocal(const GridView &g, const double *n_HI, const double *leaf_boxes,
@@ -1567,3 +1881,4 @@ hipError_t launch_sample(int precision, int what, double p0, double p1, double p
 }
 
 }  // namespace colt
+

@@ -17,7 +17,11 @@ hipError_t launch_transport(int precision, bool cams, const LaunchView &L, const
 // grid_kind: the grid kind of a one-job launch (0 Cartesian, 1 octree)
 hipError_t transport_occupancy(int precision, bool cams, bool single, int grid_kind, int block,
                                int *blocks_per_cu);
-hipError_t launch_plan(const PlanView &P, bool advance, hipStream_t s);
+// k_plan (advance = false) before a transport launch, k_advance after it
+hipError_t launch_plan(const LaunchView &L, bool advance, hipStream_t s);
+hipError_t launch_peel(int precision, const JobView &J, unsigned long long *work, int march_min,
+                       int grid, hipStream_t s);
+hipError_t peel_occupancy(int precision, int grid_kind, int *blocks_per_cu);
 hipError_t launch_nonlocal(const GridView &g, const double *n_HI, const double *leaf_boxes,
                            int64_t n, double f_nl, void *ad, void *af, hipStream_t s);
 hipError_t launch_voigt(int precision, int64_t n, const double *a, const double *x, double *out,

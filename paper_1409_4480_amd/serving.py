@@ -22,21 +22,21 @@ import numpy as np
 
 from . import colt
 
-CELL_BYTES = 64 + 32 + 16 + 8 + 8      # FP64 + FP32 records, aux (both), n_HI
+# per cell: line records (FP64 64 B, FP32 32 B), scattering-only records
+# (g, non-local and Jeans a tau: FP64 32 B, FP32 16 B) and n_HI
+CELL_BYTES = 64 + 32 + 32 + 16 + 8
 
 
-def footprint(wl, record=False):
-    """Device bytes a job will hold (grid records plus tallies and records)."""
-    g, p = wl["grid"], wl["params"]
+def footprint(wl, record=False, precision=colt.FP32_BULK):
+    """Device bytes a job will hold: its grid's records (estimated here) and
+    the job's own memory (as the library computes it: tallies, records,
+    suspend arrays, next-event task buffer)."""
+    g = wl["grid"]
     n_cells = int(np.asarray(g["n_HI"]).size)
-    n = CELL_BYTES * n_cells + 8 * (int(p.get("n_bins", 0)) + 2)
-    cams = p.get("cam_dir")
-    n_cams = 0 if cams is None else np.asarray(cams).size // 3
-    n += 8 * n_cams * (int(p.get("cam_nbins", 0)) + int(p.get("cam_npix", 0)) ** 2)
+    n = CELL_BYTES * n_cells
     if g.get("child") is not None:                     # child table, base table,
         n += (4 + 24) * n_cells + 4 * 128 ** 3          # six neighbour links per leaf
-    if record:
-        n += 32 * int(p["n_photons"]) * (1 + n_cams)
+    n += colt.job_footprint(wl["source"], wl["params"], precision, record)
     return n + (64 << 10)
 
 
@@ -77,7 +77,7 @@ class Server:
                        key=lambda i: workloads[i].get("arrival", 0.0) if realtime else 0.0)
         pending = deque(order)
         for i in order:
-            if footprint(workloads[i], self.record) > self.budget:
+            if footprint(workloads[i], self.record, self.precision) > self.budget:
                 raise colt.ColtError(f"job {i} needs more than the memory budget")
         torch = self._torch
         streams = [torch.cuda.Stream() for _ in range(self.depth)]
@@ -95,7 +95,7 @@ class Server:
                 i = pending[0]
                 wl = workloads[i]
                 arrival = wl.get("arrival", 0.0) if realtime else 0.0
-                need = footprint(wl, self.record)
+                need = footprint(wl, self.record, self.precision)
                 if arrival > now or used + need > self.budget:
                     break
                 pending.popleft()

@@ -16,7 +16,7 @@ import oracle
 from paper_1409_4480_amd import colt
 from paper_1409_4480_amd import galaxy as gx
 from paper_1409_4480_amd import observables as ob
-from tests.test_gpu_parity import FLIP_LOCAL, compare_records, oracle_grid, say
+from tests.test_gpu_parity import compare_records, measured_flip, oracle_grid, say
 
 pytestmark = pytest.mark.gpu
 
@@ -32,7 +32,7 @@ def run_models(names, n_photons, precision=colt.FP32_BULK):
     say(f"[gpu] galaxy models {names}: {[wl['leaves'] for wl in wls]} leaves, "
         f"{n_photons} photons each, precision {precision}")
     try:
-        colt.transport(jobs)
+        colt.transport_all(jobs)
         return wls, [j.tally() for j in jobs]
     finally:
         for j in jobs:
@@ -49,7 +49,7 @@ def test_galaxy_fp64_histories_match_the_oracle():
     g = colt.run(wl, precision=colt.FP64, record=True, max_events=cap)
     r = oracle.run(oracle_grid(wl["grid"]), wl["source"], wl["params"], records=True)
     size = wl["grid"]["box_max"][0] - wl["grid"]["box_min"][0]
-    compare_records(g, r, size, peel=True, flip=FLIP_LOCAL)
+    compare_records(g, r, size, peel=True, flip=measured_flip(wl))
     assert g["counters"]["escaped"] + g["counters"]["capped"] == n
 
 

@@ -1,0 +1,186 @@
+"""Preemption of the persistent transport launch (stop requests from the host,
+or a camera job's next-event task buffer filling up) and exact resumption,
+the per-stream completion events of a job, and the Jeans core-skipping mode.
+
+A stopped launch suspends every photon in flight at the end of a pass of its
+wave loop; the next launch resumes them.  Every photon's random stream depends
+only on (seed, id) and its state is saved whole, so a job run with any number
+of stops gives the same histories bit for bit, and the same tallies up to the
+order of floating-point atomic sums, as a job run straight through.
+"""
+import ctypes
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_4480_amd import colt, inputs
+from tests.test_gpu_parity import compare_records, measured_flip, say
+
+pytestmark = pytest.mark.gpu
+
+PC = inputs.PC
+EVENT_COUNTERS = ("emitted", "escaped", "absorbed", "scat_hi", "scat_dust", "crossings",
+                  "peels", "upar_tries", "peel_crossings", "capped")
+TOKEN = 7
+
+
+def same_results(a, b, tally_rtol=0.0):
+    for k in ("x", "nscat", "status", "pos"):
+        assert np.array_equal(a["records"][k], b["records"][k]), k
+    assert np.array_equal(a["spectrum"], b["spectrum"])
+    for name in EVENT_COUNTERS:
+        assert a["counters"][name] == b["counters"][name], name
+    for key in ("cam_spec", "cam_img"):
+        if a[key].size:
+            scale = max(np.abs(a[key]).max(), 1e-300)
+            assert np.allclose(a[key], b[key], rtol=tally_rtol, atol=1e-13 * scale), key
+    if a["records"]["peel"].size:
+        assert np.allclose(a["records"]["peel"], b["records"]["peel"], rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("prec", [colt.FP64, colt.FP32_BULK])
+def test_stopped_before_it_starts_then_resumed(prec):
+    """With the stop word already set the launch makes one pass and suspends
+    its photons; the job reports them unfinished, and the next launch
+    completes it with every history equal to an uninterrupted run's."""
+    wl = inputs.dusty_sphere(n=16, tau0=1e5, n_photons=20000, seed=31)
+    say(f"[gpu] stop before start, precision {prec}")
+    ref = colt.run(wl, precision=prec, record=True)
+    g = colt.Grid(wl["grid"])
+    j = colt.Job(g, wl["source"], wl["params"], precision=prec, record=True)
+    try:
+        colt.stop_set(TOKEN, True)
+        colt.transport([j], stop_token=TOKEN)
+        nxt, n_susp, ids = j.pending(max_ids=1 << 20)
+        say(f"    after the stopped launch: next id {nxt}, {n_susp} suspended")
+        assert not j.complete
+        assert 0 < n_susp <= nxt <= wl["params"]["n_photons"]
+        assert len(ids) == n_susp and np.all(np.diff(ids.astype(np.int64)) > 0)
+        assert ids.max() < nxt
+        colt.stop_set(TOKEN, False)
+        n = colt.transport_all([j])
+        out = j.tally()
+        say(f"    completed in {n} more launch(es)")
+    finally:
+        colt.stop_set(TOKEN, False)
+        j.release()
+        g.release()
+    same_results(ref, out)
+
+
+def test_repeated_stops_during_the_run():
+    """The stop word set while the kernel runs, several times: each launch
+    stops within a few passes, and the finished job equals an uninterrupted
+    run photon by photon (FP64 records and tallies)."""
+    wl = inputs.dusty_sphere(n=32, tau0=1e6, n_photons=200_000, seed=32)
+    say("[gpu] stops during the run, FP64 200k photons")
+    ref = colt.run(wl, precision=colt.FP64, record=True)
+    g = colt.Grid(wl["grid"])
+    j = colt.Job(g, wl["source"], wl["params"], precision=colt.FP64, record=True)
+    stops = 0
+    try:
+        for k in range(8):
+            colt.stop_set(TOKEN, False)
+            colt.transport([j], stop_token=TOKEN)
+            time.sleep(0.002 * (k + 1))
+            colt.stop_set(TOKEN, True)
+            nxt, n_susp, _ = j.pending()
+            if n_susp or nxt < wl["params"]["n_photons"]:
+                stops += 1
+            say(f"    launch {k}: next id {nxt}, {n_susp} suspended")
+            if j.complete:
+                break
+        colt.stop_set(TOKEN, False)
+        colt.transport_all([j])
+        out = j.tally()
+    finally:
+        colt.stop_set(TOKEN, False)
+        j.release()
+        g.release()
+    assert stops >= 2, stops
+    same_results(ref, out)
+
+
+@pytest.mark.parametrize("case", ["sphere_64cams", "halo_8cams", "octree_4cams"])
+def test_small_task_buffer_gives_the_same_results(case):
+    """Camera jobs whose next-event task buffer is far too small for the job:
+    the transport stops every time it nears full, the march kernel drains it,
+    and the next launch resumes.  Histories and per-photon camera sums equal a
+    run with the default buffer."""
+    if case == "sphere_64cams":
+        m = 64
+        i = np.arange(m) + 0.5
+        z = 1 - 2 * i / m
+        phi = np.pi * (1 + 5 ** 0.5) * i
+        cams = np.stack([np.sqrt(1 - z * z) * np.cos(phi), np.sqrt(1 - z * z) * np.sin(phi), z], 1)
+        wl = inputs.static_sphere(n=8, tau0=3e2, n_photons=300, seed=64, isotropic=False,
+                                  recoil=True, cameras=cams, cam_nbins=50, cam_npix=4)
+        small, prec = 1 << 17, colt.FP64
+    elif case == "halo_8cams":
+        wl = inputs.halo(n=32, n_photons=3000, seed=8, npix=32, n_bins=100)
+        wl["params"]["max_events"] = 3000
+        small, prec = 1 << 16, colt.FP32_BULK
+    else:
+        wl = inputs.nfw_octree(base_level=3, max_extra=3, leaves_target=(4000, 9000), turb_n=16,
+                               n_photons=1000, npix=32, n_bins=100, tau0_max=1e5)
+        wl["params"]["max_events"] = 2000
+        small, prec = 1 << 15, colt.FP32_BULK
+    cap = wl["params"].get("max_events", 0)
+    say(f"[gpu] {case}: default task buffer, then {small} slots")
+    ref = colt.run(wl, precision=prec, record=True, max_events=cap)
+    out = colt.run(dict(wl, params=dict(wl["params"], march_tasks=small)), precision=prec,
+                   record=True, max_events=cap)
+    say(f"    launches: {ref['launches']} and {out['launches']}")
+    assert out["launches"] > max(ref["launches"], 2)
+    same_results(ref, out, tally_rtol=1e-12)
+    assert ref["records"]["peel"].sum() > 0
+
+
+def test_tally_waits_for_the_launches_on_every_stream():
+    """A job's slices launched on two streams: tally(wait) waits for both
+    (the long first slice as well as the short second one)."""
+    import torch
+    wl = inputs.dusty_sphere(n=32, tau0=1e6, n_photons=100_000, seed=33)
+    g = colt.Grid(wl["grid"])
+    j = colt.Job(g, wl["source"], wl["params"], precision=colt.FP64)
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        torch.cuda.synchronize()
+        colt.transport([j], photons_per_job=99_999, stream=ctypes.c_void_p(a.cuda_stream))
+        colt.transport([j], photons_per_job=1, stream=ctypes.c_void_p(b.cuda_stream))
+        out = j.tally(wait=True)
+        c = out["counters"]
+        assert c["emitted"] == 100_000 == c["escaped"] + c["absorbed"]
+        assert out["spectrum"].sum() == c["escaped"]
+    finally:
+        j.release()
+        g.release()
+
+
+def test_jeans_core_skipping_matches_the_oracle():
+    """x_crit mode 3 (Sec. 3.2.4, eq. atau0J): a tau_J of the scattering cell.
+    The device's per-cell a tau_J equals the oracle's, and FP64 histories
+    through a 32^3 halo are the oracle's photon by photon, up to the histories
+    that rounding alone turns (the oracle's own share under a rounding
+    perturbation is 3 per cent here: the Jeans x_crit of ~17 in the dense
+    cells sends core photons far into the wing at every skip)."""
+    wl = inputs.halo(n=32, n_photons=400, seed=34, npix=16, n_bins=100, f_nl=0.0)
+    wl["params"]["xcrit_mode"] = 3
+    g = colt.Grid(wl["grid"])
+    f = g.fields()
+    g.release()
+    want = np.array([oracle.atau_jeans(T, n) for T, n in
+                     zip(wl["grid"]["T"], wl["grid"]["n_HI"])])
+    assert np.allclose(f[:, 10], want, rtol=1e-13, atol=0)
+    cap = 4000
+    wl["params"]["max_events"] = cap
+    say("[gpu] halo 32^3 Jeans core-skipping, FP64 with records")
+    gout = colt.run(wl, precision=colt.FP64, record=True, max_events=cap)
+    r = oracle.run(wl["grid"], wl["source"], wl["params"], records=True)
+    compare_records(gout, r, 200 * PC, peel=True, flip=measured_flip(wl))
+    # Jeans skipping removes more core scatterings than none at all
+    wl0 = dict(wl, params=dict(wl["params"], xcrit_mode=0))
+    r0 = oracle.run(wl0["grid"], wl0["source"], wl0["params"], records=True)
+    assert gout["counters"]["scat_hi"] < r0["counters"]["scat_hi"]

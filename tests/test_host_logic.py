@@ -5,18 +5,31 @@ import numpy as np
 from paper_1409_4480_amd import inputs, serving
 
 
+def up(n):
+    """An allocation of the library: whole 256-byte blocks, at least one."""
+    return max((n + 255) // 256 * 256, 256)
+
+
 def test_footprint_grows_with_what_a_job_holds():
-    small = inputs.static_sphere(n=16, tau0=1e4, n_photons=1000, seed=1)
-    big = inputs.static_sphere(n=32, tau0=1e4, n_photons=1000, seed=1)
+    n = 1000
+    small = inputs.static_sphere(n=16, tau0=1e4, n_photons=n, seed=1)
+    big = inputs.static_sphere(n=32, tau0=1e4, n_photons=n, seed=1)
     base = serving.footprint(small)
     # cells: every record of both precisions per cell
     assert serving.footprint(big) - base == serving.CELL_BYTES * (32 ** 3 - 16 ** 3)
-    # per-photon records: final x, counts, position and one peel sum per camera
-    assert serving.footprint(small, record=True) - base == 32 * 1000
-    cams = inputs.static_sphere(n=16, tau0=1e4, n_photons=1000, seed=1,
+    # per-photon records: final x, counts, status, position, peel sums (none)
+    assert serving.footprint(small, record=True) - base == \
+        up(8 * n) + 2 * up(4 * n) + up(24 * n) + up(0)
+    # cameras: their table, spectra and images, and the next-event task buffer
+    # of at least 2^20 slots (64 bytes each in FP32-bulk)
+    cams = inputs.static_sphere(n=16, tau0=1e4, n_photons=n, seed=1,
                                 cameras=np.eye(3), cam_nbins=50, cam_npix=8)
     extra = serving.footprint(cams) - serving.footprint(small)
-    assert extra == 8 * 3 * (50 + 8 * 8)
+    tallies = up(96 * 3) - up(96) + up(8 * 3 * 50) - up(8) + up(8 * 3 * 64) - up(8)
+    assert extra == tallies + 64 * (1 << 20)
+    # a job's suspended-photon store holds at most one record per photon
+    one = inputs.static_sphere(n=16, tau0=1e4, n_photons=1, seed=1)
+    assert base - serving.footprint(one) == 2 * (up(128 * n) - up(128))
 
 
 def test_summary_percentiles_and_rate():
