@@ -244,6 +244,22 @@ colt_status colt_emit(colt_grid grid, const colt_source_desc *src,
 colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
                            void *stream);
 
+/* colt_transport for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and results, but nothing is allocated.  The launch table lives in a
+ * fixed device array of 40 KB that each GPU holds until the process ends
+ * (found once per device on the first call); job views reach it through
+ * kernel arguments.  Limits: at most 64 jobs of one precision per call; a job
+ * may be launched this way on at most 4 streams (the completion events made
+ * with the job); stop_token only once colt_stop_set has been called;
+ * time_kernel is ignored.  Every call on one GPU shares its table, which keeps
+ * the last call's contents: calls that overlap on one GPU (other streams, not
+ * yet complete) race, so order them on one stream or synchronise.  Errors as
+ * colt_transport, plus COLT_ERR_ARG (more than 64 jobs) and COLT_ERR_STATE
+ * (a fifth stream, or stop words not yet made). */
+colt_status colt_transport_static(const colt_job *jobs, int32_t n_jobs,
+                                  const colt_launch *launch, void *stream);
+
 /* Sets (value != 0) or clears the stop word `token` (1..63).  Transport
  * launches started with that stop_token stop within about 32 passes of their
  * wave loop, suspending their photons in flight; a launch started while the

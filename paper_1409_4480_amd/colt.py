@@ -25,7 +25,8 @@ EXPORTS = ["colt_init_grid", "colt_emit", "colt_transport", "colt_tally", "colt_
            "colt_grid_bytes", "colt_job_bytes", "colt_last_kernel_ms", "colt_release_job",
            "colt_release_grid", "colt_last_error", "colt_grid_fields", "colt_eval_voigt",
            "colt_sample", "colt_grid_nonlocal", "colt_graph_create", "colt_graph_launch",
-           "colt_graph_release", "colt_stop_set", "colt_job_pending", "colt_job_footprint"]
+           "colt_graph_release", "colt_stop_set", "colt_job_pending", "colt_job_footprint",
+           "colt_transport_static"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -100,6 +101,8 @@ def lib():
         L.colt_emit.argtypes = [vp, ctypes.POINTER(SourceDesc), ctypes.POINTER(JobParams),
                                 ctypes.POINTER(vp)]
         L.colt_transport.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(Launch), vp]
+        L.colt_transport_static.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
+                                            ctypes.POINTER(Launch), vp]
         L.colt_tally.argtypes = [vp, ctypes.POINTER(TallyOut), ctypes.c_int32]
         L.colt_job_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64),
                                       ctypes.POINTER(ctypes.c_uint64)]
@@ -134,7 +137,7 @@ def lib():
                      "colt_job_status", "colt_release_grid", "colt_grid_fields",
                      "colt_eval_voigt", "colt_sample", "colt_grid_nonlocal",
                      "colt_graph_create", "colt_graph_launch", "colt_stop_set",
-                     "colt_job_pending"):
+                     "colt_job_pending", "colt_transport_static"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib

@@ -299,19 +299,28 @@ struct colt_job_s {
     uint64_t h_susp = 0;             // suspended photons at the last refresh
     bool uncertain = false;          // a launch that may have stopped is pending
     // one event per stream the job's launches ran on (tally and release wait
-    // on all of them)
+    // on all of them), taken first from events created with the job
     std::vector<std::pair<hipStream_t, hipEvent_t>> ev;
+    std::vector<hipEvent_t> spare_ev;
 };
 
 namespace {
 
-hipError_t job_event(colt_job j, hipStream_t s, hipEvent_t *out)
+// The job's completion event for stream s: the one it already has there, else
+// one created with the job, else (when allowed) a new one.
+hipError_t job_event(colt_job j, hipStream_t s, hipEvent_t *out, bool may_create = true)
 {
     for (auto &e : j->ev)
         if (e.first == s) { *out = e.second; return hipSuccess; }
     hipEvent_t e = nullptr;
-    const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
-    if (r != hipSuccess) return r;
+    if (!j->spare_ev.empty()) {
+        e = j->spare_ev.back();
+        j->spare_ev.pop_back();
+    } else {
+        if (!may_create) return hipErrorOutOfMemory;
+        const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r != hipSuccess) return r;
+    }
     j->ev.emplace_back(s, e);
     *out = e;
     return hipSuccess;
@@ -825,9 +834,15 @@ colt_status colt_emit(colt_grid g, const colt_source_desc *src, const colt_job_p
     if (e == hipSuccess && p->record)
         e = hipMemsetAsync(v.rec_peel, 0, std::max<size_t>(std::max<uint64_t>(N, 1) * nc, 1) * 8, s);
     if (e == hipSuccess) e = hipMemsetAsync(v.ctl, 0, sizeof(JobCtl), s);
+    for (int i = 0; e == hipSuccess && i < kJobEvents; ++i) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) j->spare_ev.push_back(ev);
+    }
     // host tables must outlive the asynchronous copies
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
+        for (hipEvent_t ev : j->spare_ev) (void)hipEventDestroy(ev);
         m.release_all();
         delete j;
         return fail(COLT_ERR_HIP, "job set-up failed: %s", hipGetErrorString(e));
@@ -902,6 +917,7 @@ void colt_release_job(colt_job j)
     if (!j) return;
     (void)job_wait(j);
     for (auto &e : j->ev) (void)hipEventDestroy(e.second);
+    for (hipEvent_t e : j->spare_ev) (void)hipEventDestroy(e);
     j->mem.release_all();
     if (j->grid) j->grid->jobs.fetch_sub(1);
     delete j;
@@ -1030,8 +1046,14 @@ hipError_t launch_sequence(int prec, bool cams, const LaunchView &L,
 
 }  // namespace
 
-colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
-                           void *stream)
+namespace {
+
+// Both transport entry points.  fixed: the launch table is the device's fixed
+// array (colt_transport_static) and nothing is allocated -- no launch table,
+// no stop words, no timing events, no job events beyond those made with the
+// jobs; otherwise the table comes from the jobs' allocator through the pool.
+colt_status transport_impl(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
+                           void *stream, bool fixed)
 {
     if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(COLT_ERR_ARG, "bad job list");
     hipStream_t s = (hipStream_t)stream;
@@ -1039,11 +1061,16 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
     if (block < 64 || block > 256 || block % 64)
         return fail(COLT_ERR_ARG, "block must be 64, 128, 192 or 256");
     const uint64_t quota = launch ? launch->photons_per_job : 0;
-    const bool timed = launch && launch->time_kernel;
+    bool timed = launch && launch->time_kernel;
     const int token = launch ? launch->stop_token : 0;
     if (token < 0 || token >= kStopTokens) return fail(COLT_ERR_ARG, "stop token 0..%d", kStopTokens - 1);
     const int *stop_host = nullptr;
     if (token) {
+        if (fixed) {
+            std::lock_guard<std::mutex> lk(g_stop_mu);
+            if (!g_stop_words)
+                return fail(COLT_ERR_STATE, "stop words not allocated yet (call colt_stop_set first)");
+        }
         int *w = stop_words();
         if (!w) return fail(COLT_ERR_NOMEM, "stop words allocation failed");
         int *dw = nullptr;
@@ -1080,18 +1107,38 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
             for (auto &e : j->ev)
                 if (e.first != s) HIP_TRY(hipStreamWaitEvent(s, e.second, 0));
         }
+        if (fixed) {
+            // every job must have an event for this stream before anything runs
+            for (colt_job j : members) {
+                bool ok = !j->spare_ev.empty();
+                for (auto &e : j->ev) ok = ok || e.first == s;
+                if (!ok) return fail(COLT_ERR_STATE, "a job launched on more than %d streams", kJobEvents);
+            }
+        }
         int grid = 0;
         const colt_status st = launch_shape(prec, cams, views, work, block,
                                             launch ? launch->blocks_per_cu : 0, &grid);
         if (st != COLT_OK) return st;
         const TableLayout t = table_layout(nj);
-        LaunchBuf *b = acquire_launch_buf(t.bytes, members[0]->mem.alloc, members[0]->mem.custom);
-        if (!b) return fail(COLT_ERR_NOMEM, "launch table allocation failed");
-        std::memset(b->host, 0, t.bytes);
-        std::memcpy((char *)b->host + t.jobs, views.data(), sizeof(JobView) * nj);
-        HIP_TRY(hipMemcpyAsync(b->dev, b->host, t.bytes, hipMemcpyHostToDevice, s));
-        const LaunchView L = table_view((char *)b->dev, t, nj, quota, march_min_of(launch, prec),
-                                        stop_host);
+        LaunchBuf *b = nullptr;
+        char *table = nullptr;
+        if (fixed) {
+            if (nj > kStaticJobs || t.bytes > kStaticTableBytes)
+                return fail(COLT_ERR_ARG, "at most %d jobs of one precision per call", kStaticJobs);
+            void *p = nullptr;
+            HIP_TRY(static_table(&p));
+            table = (char *)p;
+            HIP_TRY(put_views(views.data(), nj, (JobView *)(table + t.jobs), s));
+        } else {
+            b = acquire_launch_buf(t.bytes, members[0]->mem.alloc, members[0]->mem.custom);
+            if (!b) return fail(COLT_ERR_NOMEM, "launch table allocation failed");
+            std::memset(b->host, 0, t.bytes);
+            std::memcpy((char *)b->host + t.jobs, views.data(), sizeof(JobView) * nj);
+            HIP_TRY(hipMemcpyAsync(b->dev, b->host, t.bytes, hipMemcpyHostToDevice, s));
+            table = (char *)b->dev;
+        }
+        const LaunchView L = table_view(table, t, nj, quota, march_min_of(launch, prec), stop_host);
+        if (fixed) timed = false;
         if (timed && !g_t0) {
             HIP_TRY(hipEventCreate(&g_t0));
             HIP_TRY(hipEventCreate(&g_t1));
@@ -1099,7 +1146,7 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
         HIP_TRY(launch_sequence(prec, cams, L, views, grid, block, L.march_min, s,
                                 timed ? g_t0 : nullptr, timed ? g_t1 : nullptr));
         if (timed) g_timed = true;
-        HIP_TRY(hipEventRecord(b->done, s));
+        if (b) HIP_TRY(hipEventRecord(b->done, s));
         for (colt_job j : members) {
             if (!j->uncertain && !may_stop) {
                 const uint64_t left = j->params.n_photons - j->h_cursor;
@@ -1109,11 +1156,28 @@ colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_laun
                 j->uncertain = true;
             }
             hipEvent_t ev = nullptr;
-            HIP_TRY(job_event(j, s, &ev));
+            const hipError_t e = job_event(j, s, &ev, !fixed);
+            if (e == hipErrorOutOfMemory && fixed)
+                return fail(COLT_ERR_STATE, "a job launched on more than %d streams", kJobEvents);
+            HIP_TRY(e);
             HIP_TRY(hipEventRecord(ev, s));
         }
     }
     return COLT_OK;
+}
+
+}  // namespace
+
+colt_status colt_transport(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,
+                           void *stream)
+{
+    return transport_impl(jobs, n_jobs, launch, stream, false);
+}
+
+colt_status colt_transport_static(const colt_job *jobs, int32_t n_jobs,
+                                  const colt_launch *launch, void *stream)
+{
+    return transport_impl(jobs, n_jobs, launch, stream, true);
 }
 
 colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_launch *launch,

@@ -21,6 +21,13 @@ constexpr int kTaskSubs = 32;
 constexpr int kTaskChunk = 8;
 // Host stop words (colt_stop_set tokens 1 .. kStopTokens-1).
 constexpr int kStopTokens = 64;
+// Completion events created with each job, so that launches on up to this many
+// streams record them without creating any.
+constexpr int kJobEvents = 4;
+// The allocation-free launch path (colt_transport_static): jobs per launch and
+// bytes of its per-device launch table.
+constexpr int kStaticJobs = 64;
+constexpr size_t kStaticTableBytes = 40960;
 // Lanes in flight that keep a wave ray tracing (measured best on the 64^3
 // dusty sphere: 16 of 64 lanes).
 constexpr int kDefaultMarchMinFp32 = 16;

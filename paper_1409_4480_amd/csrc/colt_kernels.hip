@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "colt_device.h"
 #include "colt_internal.h"
 #include "colt_launch.h"
@@ -1732,6 +1734,65 @@ __global__ __launch_bounds__(256) void k_sample(int what, double p0, double p1, 
         const int64_t m = (int64_t)p0;
         for (int64_t j = 0; j < m; ++j) out[i * m + j] = (double)rng.next();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Launch table of the allocation-free entry point (colt_transport_static):
+// one fixed device array, `scratch`, held by every GPU the library runs on
+// until the process ends.  Job views reach it through k_put_views, whose
+// kernel arguments carry them (no host staging buffer, no copy from pageable
+// memory); k_plan fills the rest.  Host code addresses the array only through
+// the pointer hipGetSymbolAddress gives on each device (the array's name is a
+// host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticTableBytes];
+
+constexpr int kViewsPerPut = 7;
+struct ViewChunk {
+    JobView v[kViewsPerPut];
+    int32_t n, first;
+};
+static_assert(sizeof(ViewChunk) + sizeof(void *) <= 4096, "kernel arguments fit 4 KB");
+
+__global__ void k_put_views(ViewChunk c, JobView *dst)
+{
+    const int i = threadIdx.x;
+    if (i < c.n) dst[c.first + i] = c.v[i];
+}
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+hipError_t static_table(void **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t put_views(const JobView *views, int n, JobView *dst, hipStream_t s)
+{
+    for (int first = 0; first < n; first += kViewsPerPut) {
+        ViewChunk c{};
+        c.n = (n - first < kViewsPerPut) ? n - first : kViewsPerPut;
+        c.first = first;
+        for (int i = 0; i < c.n; ++i) c.v[i] = views[first + i];
+        hipLaunchKernelGGL(k_put_views, dim3(1), dim3(64), 0, s, c, dst);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,10 @@ hipError_t launch_plan(const LaunchView &L, bool advance, hipStream_t s);
 hipError_t launch_peel(int precision, const JobView &J, unsigned long long *work, int march_min,
                        int grid, hipStream_t s);
 hipError_t peel_occupancy(int precision, int grid_kind, int *blocks_per_cu);
+// The current device's fixed launch table for colt_transport_static (its
+// address found once per device) and the kernel that writes job views into it.
+hipError_t static_table(void **ptr);
+hipError_t put_views(const JobView *views, int n, JobView *dst, hipStream_t s);
 hipError_t launch_nonlocal(const GridView &g, const double *n_HI, const double *leaf_boxes,
                            int64_t n, double f_nl, void *ad, void *af, hipStream_t s);
 hipError_t launch_voigt(int precision, int64_t n, const double *a, const double *x, double *out,
