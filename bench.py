@@ -24,25 +24,38 @@ sys.path.insert(0, ROOT)
 METRIC = "Lyα scatterings/sec on 1 MI355X (mixed vs FP64 plain); p50/p99 job latency"
 VALU_PEAK = 256 * 4 * 16 * 2.4e9      # lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz
 
-# Algorithmic VALU lane-op cost per counted event of the method (FP32-bulk
-# arithmetic; transcendentals and 32-bit integer multiplies at quarter rate).
-# The derivation is written out in the design notes.
-OPS_FP32 = {"uniform": 33, "scat_hi": 400, "upar_tries": 24, "crossings": 65,
-            "peels": 40, "peel_crossings": 60, "scat_dust": 120, "emitted": 200}
-# uniforms per event: 3 per u_par candidate; u_perp (2), mu, phi and tau per
-# H I scattering; albedo, mu, phi, tau per dust scattering; mu, phi, tau per
-# emission; one channel draw per interaction in dusty cells
-DRAWS_PER = {"upar_tries": 3, "scat_hi": 5, "scat_dust": 4, "emitted": 3}
-
-# HBM bytes per launch of the FP32-bulk transport kernel on this workload,
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration
-# (profiles/k_transport_fp32_dusty_sphere_64.md).  They hold for the kernel
-# sources they were taken on; for any other sources traffic is reported null.
-TRAFFIC = {"sources_sha256": "c119bbd8e96942e2d65facb42e923d5adfa9ccef2760f0e02b4bae999963ee52",
-           "fetch_bytes": 35268615, "write_bytes": 23014752}
-KERNEL_SOURCES = ["colt_kernels.hip", "colt_device.h", "colt_internal.h"]
+# Algorithmic VALU lane-ops per unit of work, as the hot-path scope table
+# derives them for this method (non-packed lane-op slots; transcendentals and
+# 32-bit integer multiplies at quarter rate, i.e. four slots):
+#   one H I scattering with n u_par candidates: (8 + 3 (n - 1)) uniforms of ~25
+#   integer ops (Philox4x32-10), (10 + 2 n) transcendentals of 4 slots, ~150
+#   FP32 and ~20 FP64 flops, i.e. 335 + 83 n (about 500 for core scatterings,
+#   1100 for 3 <= |x| < 9);
+#   one cell crossing, of the transport or of a next-event march: one H(a,x)
+#   (~15 flops and an exp) and ~15 FP64 ops, i.e. 34.
+def ops_per_scattering(n_iter):
+    return 335.0 + 83.0 * n_iter
 
 
+OPS_PER_CROSSING = 34.0
+
+
+def algorithmic_ops(c):
+    """Lane-ops of a launch from its event counters."""
+    n_iter = c["upar_tries"] / max(c["scat_hi"], 1)
+    return (c["scat_hi"] * ops_per_scattering(n_iter) +
+            (c["crossings"] + c["peel_crossings"]) * OPS_PER_CROSSING)
+
+
+# Figures of the FP32-bulk transport kernel on this workload from rocprofv3
+# counters of the committed profile (profiles/k_transport_fp32_dusty_sphere_64.md):
+# HBM bytes per launch from FETCH_SIZE and WRITE_SIZE scaled by a plain-copy
+# calibration, and the VALU lane-instructions the hardware executed
+# (SQ_INSTS_VALU x 64 x lane use) with the kernel time of that run.  They hold
+# for the kernel sources they were taken on; for other sources they are null.
+PROFILE = {"sources_sha256": "",
+           "fetch_bytes": None, "write_bytes": None,
+           "valu_lane_instructions": None, "kernel_ms": None}
 def kernel_sources_sha256():
     import hashlib
     h = hashlib.sha256()
@@ -52,21 +65,10 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    if TRAFFIC["sources_sha256"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
-        return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+def profile_figures():
+    if PROFILE["sources_sha256"] and PROFILE["sources_sha256"] == kernel_sources_sha256():
+        return PROFILE
     return None
-
-
-def algorithmic_ops(c, dusty=True):
-    draws = sum(DRAWS_PER[k] * c[k] for k in DRAWS_PER)
-    if dusty:
-        draws += c["scat_hi"] + c["scat_dust"] + c["absorbed"]
-    ops = OPS_FP32["uniform"] * draws
-    for k in ("scat_hi", "upar_tries", "crossings", "peels", "peel_crossings", "scat_dust",
-              "emitted"):
-        ops += OPS_FP32[k] * c[k]
-    return ops
 
 
 def workload(n_photons, seed):
@@ -97,43 +99,69 @@ def cpu_baseline(n_photons_full, budget_s=15.0):
             "photons_per_s": n / dt}
 
 
-def serve_section(n_jobs):
-    """Serving stream of uneven spheres (grid 32^3-64^3, tau0 1e4-1e5,
-    1e4-5e4 photons, half with Hubble-like outflows): capacity with every job
-    arrived at once, then Poisson arrivals at 0.8 of that capacity with p50/p99
-    latency, against one job at a time in plain FP64."""
+def serve_section(n_jobs, scaled=False):
+    """The serving stream: n_jobs uniform or Hubble-expanding spheres (grid
+    32^3-128^3, tau0 log-uniform in 1e4-1e8, 1e4-1e6 photons log-uniform,
+    global core-skipping, recoil), FP32-bulk.  Capacity with every job arrived
+    at once; then Poisson arrivals at 0.8 of that capacity with p50/p99
+    latency (arrival to tallies on the host); against one job at a time in
+    plain FP64, timed on a sample of jobs spread over the stream's range of
+    scatterings per job (it would take over an hour for all 512).  scaled:
+    the smaller stream of 32^3-64^3 grids, tau0 1e4-1e5, 1e4-5e4 photons."""
     import numpy as np
     import torch
 
     from paper_1409_4480_amd import colt, inputs, serving
 
-    stream = inputs.job_stream(n_jobs=n_jobs, seed=5, n_range=(32, 64),
-                               tau_range=(1.0e4, 1.0e5), ph_range=(1.0e4, 5.0e4))
-    srv = serving.Server(epoch_photons=1 << 20, min_quota=8192)
+    if scaled:
+        stream = inputs.job_stream(n_jobs=n_jobs, seed=5, n_range=(32, 64),
+                                   tau_range=(1.0e4, 1.0e5), ph_range=(1.0e4, 5.0e4))
+        epoch, quota = 1 << 20, 8192
+        cfg = {"grid": "32^3-64^3", "tau0": "1e4-1e5", "photons": "1e4-5e4"}
+    else:
+        stream = inputs.job_stream(n_jobs=n_jobs, seed=5)
+        epoch, quota = 1 << 22, 65536
+        cfg = {"grid": "32^3-128^3", "tau0": "1e4-1e8", "photons": "1e4-1e6"}
+    srv = serving.Server(epoch_photons=epoch, min_quota=quota)
     out = srv.run(stream, realtime=False)
     batched = serving.summarize(out, srv.makespan)
+    batched["epochs"] = srv.epochs
+    print(f"# serving: capacity {batched['scatterings_per_s']:.3e} scatterings/s over "
+          f"{srv.makespan:.1f} s", file=sys.stderr, flush=True)
     rate = 0.8 * n_jobs / srv.makespan
     rng = np.random.default_rng(5)
     t = 0.0
     for wl in stream:
         t += rng.exponential(1.0 / rate)
         wl["arrival"] = t
-    srv = serving.Server(epoch_photons=1 << 20, min_quota=8192)
-    out = srv.run(stream, realtime=True)
-    poisson = serving.summarize(out, srv.makespan)
+    srv = serving.Server(epoch_photons=epoch, min_quota=quota)
+    out2 = srv.run(stream, realtime=True)
+    poisson = serving.summarize(out2, srv.makespan)
+    print(f"# serving: Poisson p50/p99 {poisson['p50_ms']:.0f}/{poisson['p99_ms']:.0f} ms",
+          file=sys.stderr, flush=True)
+    # one job at a time, FP64: a sample across the stream's job sizes (the
+    # FP32 run's scatterings per job, from small to large)
+    scat_job = np.array([o["counters"]["scat_hi"] for o in out], float)
+    order = np.argsort(scat_job)
+    picks = order[np.linspace(0, len(order) - 1, 12).round().astype(int)]
+    picks = [int(i) for i in picks if scat_job[i] <= 2e9][:10]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     scat = 0
-    for wl in stream:
-        r = colt.run(wl, precision=colt.FP64)
+    for i in picks:
+        r = colt.run(stream[i], precision=colt.FP64)
         scat += r["counters"]["scat_hi"]
     serial = time.perf_counter() - t0
-    return {"config": {"jobs": n_jobs, "grid": "32^3-64^3", "tau0": "1e4-1e5",
-                       "photons": "1e4-5e4", "precision": "FP32-bulk", "epoch_photons": 1 << 20},
+    serial_rate = scat / serial
+    return {"config": dict(cfg, jobs=n_jobs, precision="FP32-bulk", epoch_photons=epoch,
+                           scaled=scaled),
             "batched": batched,
-            "poisson": dict(poisson, rate_jobs_per_s=rate),
-            "serial_fp64": {"scatterings_per_s": scat / serial, "makespan_s": serial},
-            "speedup_batched_vs_serial_fp64": batched["scatterings_per_s"] / (scat / serial)}
+            "poisson": dict(poisson, rate_jobs_per_s=rate, offered_load=0.8),
+            "serial_fp64": {"scatterings_per_s": serial_rate, "sample_jobs": len(picks),
+                            "sample_scatterings": scat, "sample_s": serial,
+                            "sample": "jobs spread over the stream's scatterings per job "
+                                      "(up to 2e9), each alone, FP64"},
+            "speedup_batched_vs_serial_fp64": batched["scatterings_per_s"] / serial_rate}
 
 
 def precision_errors(grid, wl):
@@ -178,14 +206,44 @@ def precision_errors(grid, wl):
     return res
 
 
+def timed_job(grid, wl, precision, cap=0):
+    """Runs one job to completion (as many launches as its next-event task
+    buffer needs) and returns its counters, the wall time between device
+    synchronisations and the launch count."""
+    import torch
+
+    from paper_1409_4480_amd import colt
+    job = colt.Job(grid, wl["source"], wl["params"], precision=precision, max_events=cap)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    n = colt.transport_all([job])
+    c = job.tally(wait=True)["counters"]
+    dt = time.perf_counter() - t
+    job.release()
+    return c, dt, n
+
+
+def workload_figures(c, dt, n, extra):
+    ops = algorithmic_ops(c)
+    return dict({"scatterings_per_s": c["scat_hi"] / dt, "ms": dt * 1e3, "launches": n,
+                 "photons": c["emitted"], "photons_per_s": c["emitted"] / dt,
+                 "scatterings_per_photon": c["scat_hi"] / max(c["emitted"], 1),
+                 "peels_per_scattering": c["peels"] / max(c["scat_hi"], 1),
+                 "peel_crossings_per_s": c["peel_crossings"] / dt,
+                 "upar_tries_per_scattering": c["upar_tries"] / max(c["scat_hi"], 1),
+                 "valu_frac_algorithmic": ops / dt / VALU_PEAK,
+                 "precision": "FP32-bulk"}, **extra)
+
+
 def workloads_section(n_photons=262144, cap=2000, only=None):
-    """Throughput of the other workloads, a full photon pool each, FP32-bulk:
-    the 128^3 first-galaxy halo (8 cameras, 256^2 images, 1000 bins), the ~2e6-
-    leaf NFW octree (4 cameras, 512^2 images, non-local core-skipping estimate
-    at set-up) and an idealised first-galaxy model (WL7 on an octree, six axis
-    cameras), every photon followed for its first `cap` events -- the steady
-    state of jobs whose full histories run to ~1e6 scatterings per photon --
-    and the static slab at tau0 = 1e7 run to completion."""
+    """Throughput of the other workloads, FP32-bulk, all kernels of every
+    launch timed between device synchronisations: the 128^3 first-galaxy halo
+    (8 cameras, 256^2 images, 1000 bins), the ~2e6-leaf NFW octree (4 cameras,
+    512^2 images, non-local core-skipping estimate at set-up) and an idealised
+    first-galaxy model (WL7 on an octree, six axis cameras), a full pool of
+    photons each followed for its first `cap` events (the steady state of jobs
+    whose full histories run to ~1e6 scatterings per photon), and the static
+    slab at tau0 = 1e7 run to completion."""
     import numpy as np
     import torch
 
@@ -211,23 +269,38 @@ def workloads_section(n_photons=262144, cap=2000, only=None):
         grid = colt.Grid(wl["grid"])
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t) * 1e3
-        for rep in range(2):
-            job = colt.Job(grid, wl["source"], wl["params"], precision=colt.FP32_BULK,
-                           max_events=ev_cap)
-            torch.cuda.synchronize()
-            colt.transport([job], time_kernel=True)
-            c = job.tally(wait=True)["counters"]
-            ms = colt.last_kernel_ms()
-            job.release()
+        for rep in range(2):                      # the first run warms up
+            c, dt, n = timed_job(grid, wl, colt.FP32_BULK, ev_cap)
         grid.release()
         n_cells = int(np.asarray(wl["grid"]["n_HI"]).size)
-        out[name] = {"scatterings_per_s": c["scat_hi"] / (ms * 1e-3), "kernel_ms": ms,
-                     "photons": n_photons, "events_cap": ev_cap or None,
-                     "scatterings_per_photon": c["scat_hi"] / max(c["emitted"], 1),
-                     "peels_per_scattering": c["peels"] / max(c["scat_hi"], 1),
-                     "peel_crossings_per_s": c["peel_crossings"] / (ms * 1e-3),
-                     "grid_nodes": n_cells, "grid_setup_ms": setup_ms,
-                     "precision": "FP32-bulk"}
+        out[name] = workload_figures(c, dt, n, {"events_cap": ev_cap or None,
+                                                "grid_nodes": n_cells, "grid_setup_ms": setup_ms})
+        print(f"# {name}: {out[name]['scatterings_per_s']:.3e} scatterings/s", file=sys.stderr,
+              flush=True)
+    return out
+
+
+def full_histories_section(n_photons):
+    """The halo (128^3, its configuration: local and non-local core-skipping,
+    8 cameras) and the NFW octree (~2e6 leaves, 4 cameras) followed to the end
+    of every history, on a subsample: the job's first n_photons photon ids (the
+    same photons as in the 1e7-photon jobs).  Their histories are heavy-tailed
+    (~8e5 scatterings per halo photon on average, some over 5e6), so the last
+    photons run nearly alone and the run's time includes that tail."""
+    from paper_1409_4480_amd import colt, inputs
+
+    out = {}
+    for name, make in (("halo_128cube_8cams_full", lambda: inputs.halo(n_photons=n_photons)),
+                       ("nfw_octree_2e6_leaves_4cams_full",
+                        lambda: inputs.nfw_octree(n_photons=n_photons))):
+        wl = make()
+        grid = colt.Grid(wl["grid"])
+        c, dt, n = timed_job(grid, wl, colt.FP32_BULK)
+        grid.release()
+        out[name] = workload_figures(c, dt, n, {"sample": f"photon ids 0..{n_photons - 1} of "
+                                                          f"the 1e7-photon job, full histories"})
+        print(f"# {name}: {dt:.1f} s, {out[name]['scatterings_per_photon']:.3g} scatterings "
+              f"per photon", file=sys.stderr, flush=True)
     return out
 
 
@@ -246,8 +319,13 @@ def main():
                          "(0 or 1 skips it)")
     ap.add_argument("--no-cams", action="store_true",
                     help="skip the other workloads (cameras, octrees, galaxy model, slab)")
-    ap.add_argument("--serve-jobs", type=int, default=48,
+    ap.add_argument("--serve-jobs", type=int, default=512,
                     help="jobs in the serving stream (0 skips the serving section)")
+    ap.add_argument("--serve-scaled", action="store_true",
+                    help="serve the smaller stream (32^3-64^3, tau0 <= 1e5, <= 5e4 photons)")
+    ap.add_argument("--full-photons", type=int, default=4096,
+                    help="photons of the halo and octree followed to the end of their "
+                         "histories (0 skips)")
     ap.add_argument("--only-workload", default=None,
                     help="only run this entry of the workloads section (e.g. halo_128cube_8cams) "
                          "and print its figures")
@@ -315,6 +393,14 @@ def main():
     kern_avg_ms = float(np.mean(kern))
     ops = np.mean([algorithmic_ops(c) for c in cnt])
     achieved = ops / (kern_avg_ms * 1e-3)
+    prof = profile_figures()
+    measured = None
+    if prof:
+        lanes = prof["valu_lane_instructions"]
+        measured = {"valu_lane_instructions": lanes, "kernel_ms": prof["kernel_ms"],
+                    "achieved": lanes / (prof["kernel_ms"] * 1e-3) / 1e12,
+                    "frac": lanes / (prof["kernel_ms"] * 1e-3) / VALU_PEAK,
+                    "source": "rocprofv3 counters, profiles/k_transport_fp32_dusty_sphere_64.md"}
     result = {
         "metric": METRIC, "value": value, "unit": "scatterings/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
@@ -338,9 +424,13 @@ def main():
                      max(128 * sum(c["upar_rounds"] for c in cnt), 1)},
         "grid_setup_ms": grid_setup_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK,
+                     "traffic": (prof["fetch_bytes"] + prof["write_bytes"]) if prof else None,
                      "kernel": "k_transport<float>", "kernel_ms": kern_avg_ms,
-                     "ops_per_launch": ops},
+                     "ops_per_launch": ops,
+                     "ops_model": "335 + 83 n lane-ops per H I scattering (n u_par candidates), "
+                                  "34 per cell crossing",
+                     "measured": measured},
     }
     # the same steps fused: args.steps jobs of the workload in one persistent
     # launch (per-job queues), so that one job's long-lived last photons share
@@ -376,8 +466,10 @@ def main():
     grid.release()
     if not args.no_cams:
         result["workloads"] = workloads_section()
+    if args.full_photons > 0:
+        result["full_histories"] = full_histories_section(args.full_photons)
     if args.serve_jobs > 0:
-        result["serving"] = serve_section(args.serve_jobs)
+        result["serving"] = serve_section(args.serve_jobs, scaled=args.serve_scaled)
         result["latency_ms"] = {"p50": result["serving"]["poisson"]["p50_ms"],
                                 "p99": result["serving"]["poisson"]["p99_ms"],
                                 "of": "serving stream jobs (arrival to tallies on host)"}

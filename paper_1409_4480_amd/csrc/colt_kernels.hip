@@ -226,12 +226,13 @@ __device__ __forceinline__ bool cross_octree(const GridView &g, CellBox &c, cons
     const int up = (int)(e >> 27);
     int node = (int)(e & 0x7FFFFFFu);
     const double size = c.size * (double)(1u << up);     // exact (powers of two)
+    const double inv_size = 1.0 / size;                   // exact as well
     double lo[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double x = (d == axis) ? ((step > 0) ? c.lo[d] + c.size : c.lo[d] - c.size)
                                      : c.lo[d];
-        lo[d] = (up == 0) ? x : ::floor(x / size) * size;
+        lo[d] = (up == 0) ? x : ::floor(x * inv_size) * size;   // exact: size is 2^k
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -1178,14 +1179,16 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
     const uint32_t rtotal = L.rprefix[L.n_jobs];
     const int march_min = L.march_min;
     bool res_left = rtotal > 0, new_left = total > 0;
-    bool have = false, moving = false, stopping = false;
+    bool have = false, moving = false, stopping = false;   // stopping: a stop was seen
     uint32_t pass = 0;
     for (;;) {
-        // a stop request set before or during this pass is acted on at its end
+        // a stop request set before or during this pass is acted on at its end;
+        // only camera launches can set the device word (a task buffer near full)
         int stop_word = 0;
         if (lane == 0) {
-            stop_word = (int)__hip_atomic_load(L.stop_dev, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+            if constexpr (CAMS)
+                stop_word = (int)__hip_atomic_load(L.stop_dev, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
             if (L.stop_host && (pass % kHostPoll) == 0)
                 stop_word |= __hip_atomic_load(L.stop_host, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1345,26 +1348,27 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
             }
         }
         ++pass;
-        if (!stopping && __shfl(stop_word, 0) != 0) stopping = true;
-        if (stopping) {
-            if (have) suspend<R>(*J, p);
-            have = false;
-            moving = false;
-            new_left = false;
-            while (res_left) {
-                uint32_t b = 0;
-                if (lane == 0) b = (uint32_t)atomicAdd(L.rqueue, 64ull);
-                b = __shfl(b, 0);
-                if (b + 64u >= rtotal) res_left = false;
-                const uint32_t ri = b + (uint32_t)lane;
-                if (ri < rtotal) {
-                    const int j = SINGLE ? 0 : find_rjob(L, ri);
-                    carry_over(SINGLE ? *J_single : L.jobs[j], ri - L.rprefix[j]);
-                }
-            }
+        if (__builtin_amdgcn_readfirstlane(stop_word) != 0) {   // lane 0: all lanes are active here
+            stopping = true;
+            break;
         }
         if (!any_have && !res_left && !new_left) break;
-        if (stopping) break;
+    }
+    if (stopping) {
+        // suspend the wave's photons (all in flight at the end of a pass) and
+        // hand on the resumes no lane has taken
+        if (have) suspend<R>(*J, p);
+        while (res_left) {
+            uint32_t b = 0;
+            if (lane == 0) b = (uint32_t)atomicAdd(L.rqueue, 64ull);
+            b = __shfl(b, 0);
+            if (b + 64u >= rtotal) res_left = false;
+            const uint32_t ri = b + (uint32_t)lane;
+            if (ri < rtotal) {
+                const int j = SINGLE ? 0 : find_rjob(L, ri);
+                carry_over(SINGLE ? *J_single : L.jobs[j], ri - L.rprefix[j]);
+            }
+        }
     }
     if constexpr (CAMS) {
         if (J) close_tasks(*J, pc.tc);
