@@ -101,3 +101,14 @@ def slab_J(x, atau0):
     """Emergent angle-averaged intensity of a static uniform slab (eq. neufeld)."""
     return 1.0 / (4.0 * np.sqrt(6.0 * np.pi)) * x * x / atau0 / \
         np.cosh(np.sqrt(np.pi ** 3 / 54.0) * x ** 3 / atau0)
+
+
+def mirror_walk(x):
+    """Symmetry about zero of a sample: with the values ordered by |x|
+    (largest first), the walk of their signs; under symmetry it is a simple
+    random walk, so its largest excursion over sqrt(n) exceeds c with
+    probability at most 4 Q(c) (reflection principle, both signs)."""
+    x = np.asarray(x, float)
+    x = x[x != 0]
+    s = np.sign(x[np.argsort(-np.abs(x), kind="stable")])
+    return np.abs(np.cumsum(s)).max() / np.sqrt(len(s))
