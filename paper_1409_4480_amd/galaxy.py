@@ -6,8 +6,9 @@ total hydrogen mass through the chi parameter (eqs. MHtot, nH0, chi); an
 "Early" or "Late" ionised region (a Stromgren sphere of radius r_core, plus for
 "Late" a bipolar cone out to r_edge); a static or beta-law wind velocity field
 (eq. wind); T = 1e4 K; mapped onto an octree over (-2 r_edge, 2 r_edge)^3 by the
-Jeans, Sobolev and geometric refinement criteria of Sec. 5.1.4.  The central
-starburst of Sec. 5.3 (eq. L_Lya) sets the Lyman-alpha luminosity.
+Jeans, Sobolev and geometric refinement criteria of Sec. 5.1.4.  The source's
+luminosity is only a normalisation of the tallies (the transfer is scale-free)
+and is an argument of the observables.
 
 Classification (table models): S/W (static / wind), E/L (early / late), 5-8
 (M_H,tot = 1e5 ... 1e8 Msun); e.g. "WL7".
@@ -27,7 +28,6 @@ M_SUN = 1.98847e33           # g
 L_SUN = 3.828e33             # erg/s
 G_NEWTON = 6.67430e-8
 K_B = 1.380649e-16
-EV = 1.602176634e-12         # erg
 PC = inputs.PC
 KPC = inputs.KPC
 MPC = inputs.MPC
@@ -106,18 +106,6 @@ def stromgren_radius(n_ion_per_s, n0, T=1.0e4):
     """eq. stromgren with alpha_B = 2.5e-13 T4^-3/4 cm^3/s (cm)."""
     alpha_b = 2.5e-13 * (T / 1.0e4) ** -0.75
     return (3.0 * n_ion_per_s / (4.0 * math.pi * n0 * n0 * alpha_b)) ** (1.0 / 3.0)
-
-
-def starburst(m_h_tot_msun, eta=0.01, f_esc_ion=0.0):
-    """Central Pop III starburst (Sec. 5.3, table central_starburst, eq. L_Lya):
-    M_gas = M_H,tot / 0.75, M_* = eta M_gas, N_ion = 1e48 s^-1 (M_*/Msun),
-    L_Lya = 0.68 h nu_0 (1 - f_esc) N_ion with h nu_0 = 10.2 eV."""
-    m_gas = m_h_tot_msun / X_H
-    m_star = eta * m_gas
-    n_ion = 1.0e48 * m_star
-    l_lya = 0.68 * 10.2 * EV * (1.0 - f_esc_ion) * n_ion
-    return {"M_gas": m_gas, "M_star": m_star, "N_ion": n_ion, "L_Lya": l_lya,
-            "L_Lya_Lsun": l_lya / L_SUN, "M_vir": 10.0 * m_h_tot_msun}
 
 
 def wind_speed(r, v_inf=V_INF, r_star=R_STAR):

@@ -64,16 +64,6 @@ def test_jeans_and_stromgren_lengths():
         pytest.approx(2.0, rel=1e-12)
 
 
-def test_central_starburst_table():
-    # table central_starburst, idealised row: M_* = 1.3e[3-6] Msun, N_ion = 1.3e[51-54]
-    # s^-1, L_Lya = 3.9e[6-9] Lsun for M_H,tot = 1e[5-8] Msun at eta = 0.01
-    for k, m in enumerate(MODELS):
-        sb = gx.starburst(m)
-        assert sb["M_star"] == pytest.approx(1.3e3 * 10 ** k, rel=0.03)
-        assert sb["N_ion"] == pytest.approx(1.3e51 * 10 ** k, rel=0.03)
-        assert sb["L_Lya_Lsun"] == pytest.approx(3.9e6 * 10 ** k, rel=0.02)
-
-
 def test_wind_law_and_gradient():
     r = np.array([0.5, 1.0, 4.0, 1e6]) * gx.R_STAR
     v = gx.wind_speed(r)
