@@ -330,6 +330,22 @@ const char *colt_last_error(void);
  * k_dust (cm^-1), x_cw, g, atau_nl, atau_J (eq. atau0J). */
 colt_status colt_grid_fields(colt_grid grid, double *out);
 
+/* The neighbour links the library builds for an octree grid (host only, no
+ * device use), for inspection.  child is the grid's node table as given to
+ * colt_init_grid (-1 for a leaf); leaves are numbered in node order.  For leaf
+ * j and face f = 2 axis + (step > 0), links[6 j + f] is
+ *   0xFFFFFFFF                   the face is the domain edge;
+ *   0xFFFFFFFE                   no link (a crossing there searches the tree);
+ *   0x80000000 | up << 27 | l    leaf l lies across, up levels coarser;
+ *   n                            node n lies across at the leaf's own level and
+ *                                is refined (a crossing descends into it).
+ * The point across is the first finest-level cell beyond the face at the
+ * leaf's lowest corner.  links == NULL only reports n_leaves; otherwise it
+ * holds 6 n_leaves entries, owned by the caller.  COLT_ERR_ARG for an invalid
+ * tree (as colt_init_grid). */
+colt_status colt_octree_links(const int32_t *child, int64_t n_nodes, uint32_t *links,
+                              int64_t *n_leaves);
+
 /* H(a, x) (eq. AB) evaluated on the device in the given precision. */
 colt_status colt_eval_voigt(int32_t precision, const double *a, const double *x, int64_t n,
                             double *out, void *stream);

@@ -23,7 +23,8 @@ COUNTER_NAMES = ["emitted", "escaped", "absorbed", "scat_hi", "scat_dust", "cros
 
 EXPORTS = ["colt_init_grid", "colt_emit", "colt_transport", "colt_tally", "colt_job_status",
            "colt_grid_bytes", "colt_job_bytes", "colt_last_kernel_ms", "colt_release_job",
-           "colt_release_grid", "colt_last_error", "colt_grid_fields", "colt_eval_voigt",
+           "colt_release_grid", "colt_last_error", "colt_grid_fields", "colt_octree_links",
+           "colt_eval_voigt",
            "colt_sample", "colt_grid_nonlocal", "colt_graph_create", "colt_graph_launch",
            "colt_graph_release", "colt_stop_set", "colt_job_pending", "colt_job_footprint",
            "colt_transport_static"]
@@ -117,6 +118,8 @@ def lib():
         L.colt_release_grid.argtypes = [vp]
         L.colt_last_error.restype = ctypes.c_char_p
         L.colt_grid_fields.argtypes = [vp, _dp]
+        L.colt_octree_links.argtypes = [_ip, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint32),
+                                        ctypes.POINTER(ctypes.c_int64)]
         L.colt_grid_nonlocal.argtypes = [vp, ctypes.c_double, vp]
         L.colt_graph_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(Launch),
                                         vp, ctypes.POINTER(vp)]
@@ -137,7 +140,7 @@ def lib():
                      "colt_job_status", "colt_release_grid", "colt_grid_fields",
                      "colt_eval_voigt", "colt_sample", "colt_grid_nonlocal",
                      "colt_graph_create", "colt_graph_launch", "colt_stop_set",
-                     "colt_job_pending", "colt_transport_static"):
+                     "colt_job_pending", "colt_transport_static", "colt_octree_links"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -303,6 +306,19 @@ def _job_descs(source, params, precision=FP64, record=False, max_events=0, march
     p.max_events = int(max_events)
     p.march_tasks = int(march_tasks or params.get("march_tasks", 0))
     return s, p, (pos, w, cams)
+
+
+def octree_links(child):
+    """The neighbour links the library builds for an octree node table (host
+    only): an (n_leaves, 6) uint32 array, face 2 axis + (step > 0)."""
+    child = np.ascontiguousarray(child, np.int32)
+    n = ctypes.c_int64(0)
+    _check(lib().colt_octree_links(_ptr(child, _ip), len(child), None, ctypes.byref(n)))
+    out = np.zeros((n.value, 6), np.uint32)
+    _check(lib().colt_octree_links(_ptr(child, _ip), len(child),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                   ctypes.byref(n)))
+    return out
 
 
 def job_footprint(source, params, precision=FP64, record=False):

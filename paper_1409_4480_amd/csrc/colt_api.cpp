@@ -46,12 +46,16 @@ colt_status fail(colt_status code, const char *fmt, ...)
 
 // Octree neighbour links: for every leaf and face (2 axis + (step > 0)), the
 // node across that face at the leaf's own level, or the coarser leaf that
-// covers it there.  An entry holds the node and how many levels coarser it is,
-// (up << 27) | node; kRopeEdge marks the domain face and kRopeSearch a case the
-// encoding cannot hold (the transport then searches from the root).  Built
-// with exact integer coordinates in units of the finest cell.
-constexpr uint32_t kRopeEdge = 0xFFFFFFFFu, kRopeSearch = 0xFFFFFFFEu;
+// covers it there.  A leaf across (same level or coarser) is stored as its leaf
+// index with how many levels coarser it is, kRopeLeaf | (up << 27) | leaf, so
+// a crossing reads no node table; a refined node across (its children are
+// finer than the leaf) is stored as the node, which the crossing descends.
+// kRopeEdge marks the domain face and kRopeSearch a case the encoding cannot
+// hold (the transport then searches from the root).  Built with exact integer
+// coordinates in units of the finest cell.
+constexpr uint32_t kRopeEdge = 0xFFFFFFFFu, kRopeSearch = 0xFFFFFFFEu, kRopeLeaf = 0x80000000u;
 
+// child: the device node table (a leaf holds -(leaf index + 1)).
 void build_ropes(const int32_t *child, int64_t nn, const std::vector<int32_t> &depth,
                  const std::vector<int64_t> &order, const std::vector<int64_t> &leaf_src,
                  std::vector<uint32_t> &rope)
@@ -95,8 +99,14 @@ void build_ropes(const int32_t *child, int64_t nn, const std::vector<int32_t> &d
                     ++lvl;
                 }
                 const int up = dl - lvl;
-                if (node < (int64_t(1) << 27) && up < 32)
-                    rope[(size_t)j * 6 + face] = ((uint32_t)up << 27) | (uint32_t)node;
+                if (child[node] < 0) {
+                    // up <= 14 keeps clear of the two marker values
+                    const int64_t lf = -(int64_t)child[node] - 1;
+                    if (lf < (int64_t(1) << 27) && up <= 14)
+                        rope[(size_t)j * 6 + face] = kRopeLeaf | ((uint32_t)up << 27) | (uint32_t)lf;
+                } else if (node < (int64_t(1) << 27) && up == 0) {
+                    rope[(size_t)j * 6 + face] = (uint32_t)node;
+                }
             }
         }
     };
@@ -109,6 +119,53 @@ void build_ropes(const int32_t *child, int64_t nn, const std::vector<int32_t> &d
     for (int64_t t = 0; t < nt; ++t)
         th.emplace_back(work, nl * t / nt, nl * (t + 1) / nt);
     for (auto &x : th) x.join();
+}
+
+// Breadth-first walk of a caller's octree: every node reached exactly once
+// from the root, child indices in range, depth per node and the walk order.
+colt_status octree_walk(const int32_t *child, int64_t nn, std::vector<int32_t> &depth,
+                        std::vector<int64_t> &order)
+{
+    depth.assign(nn, -1);
+    order.clear();
+    order.reserve(nn);
+    depth[0] = 0;
+    order.push_back(0);
+    for (size_t h = 0; h < order.size(); ++h) {
+        const int64_t i = order[h];
+        const int32_t c = child[i];
+        if (c < 0) continue;
+        if ((int64_t)c + 7 >= nn || c <= 0)
+            return fail(COLT_ERR_ARG, "node %lld has child index %d out of range",
+                        (long long)i, c);
+        for (int o = 0; o < 8; ++o) {
+            if (depth[c + o] >= 0) return fail(COLT_ERR_ARG, "node %d reached twice", c + o);
+            depth[c + o] = depth[i] + 1;
+            order.push_back(c + o);
+        }
+        if (depth[i] + 1 > 40) return fail(COLT_ERR_ARG, "octree deeper than 40");
+    }
+    if ((int64_t)order.size() != nn)
+        return fail(COLT_ERR_ARG, "%lld nodes unreachable from the root",
+                    (long long)(nn - (int64_t)order.size()));
+    return COLT_OK;
+}
+
+// The device node table (a leaf holds -(leaf index + 1), leaves numbered in
+// node order) and the caller's node of every leaf.
+void node_table(const int32_t *child, int64_t nn, std::vector<int32_t> &child_dev,
+                std::vector<int64_t> &leaf_src)
+{
+    child_dev.assign(nn, 0);
+    leaf_src.clear();
+    for (int64_t i = 0; i < nn; ++i) {
+        if (child[i] >= 0) {
+            child_dev[i] = child[i];
+        } else {
+            child_dev[i] = -(int32_t)leaf_src.size() - 1;
+            leaf_src.push_back(i);
+        }
+    }
 }
 
 // Device memory from the caller's allocator (or hipMalloc), remembered for release.
@@ -425,30 +482,9 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
         if (nn > INT32_MAX / 2) return delete g, fail(COLT_ERR_ARG, "too many octree nodes");
         if (std::fabs(ext[1] / ext[0] - 1.0) > 1e-9 || std::fabs(ext[2] / ext[0] - 1.0) > 1e-9)
             return delete g, fail(COLT_ERR_ARG, "octree root box must be a cube");
-        // breadth-first walk: every node reached exactly once, depth per node
-        std::vector<int32_t> depth(nn, -1);
+        std::vector<int32_t> depth;
         std::vector<int64_t> order;
-        order.reserve(nn);
-        depth[0] = 0;
-        order.push_back(0);
-        for (size_t h = 0; h < order.size(); ++h) {
-            const int64_t i = order[h];
-            const int32_t c = d->child[i];
-            if (c < 0) continue;
-            if ((int64_t)c + 7 >= nn || c <= 0)
-                return delete g, fail(COLT_ERR_ARG, "node %lld has child index %d out of range",
-                                      (long long)i, c);
-            for (int o = 0; o < 8; ++o) {
-                if (depth[c + o] >= 0)
-                    return delete g, fail(COLT_ERR_ARG, "node %d reached twice", c + o);
-                depth[c + o] = depth[i] + 1;
-                order.push_back(c + o);
-            }
-            if (depth[i] + 1 > 40) return delete g, fail(COLT_ERR_ARG, "octree deeper than 40");
-        }
-        if ((int64_t)order.size() != nn)
-            return delete g, fail(COLT_ERR_ARG, "%lld nodes unreachable from the root",
-                                  (long long)(nn - (int64_t)order.size()));
+        if (octree_walk(d->child, nn, depth, order) != COLT_OK) return delete g, COLT_ERR_ARG;
         // base level: deepest level above which every node is refined (<= 7)
         int min_leaf_depth = 1 << 30;
         for (int64_t i = 0; i < nn; ++i)
@@ -457,17 +493,9 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
         nb = 1 << Lb;
         g->dx_cm = ext[0] / nb;
         g->view.n[0] = g->view.n[1] = g->view.n[2] = nb;
-        child_dev.assign(nn, 0);
-        for (int64_t i = 0; i < nn; ++i) {
-            if (d->child[i] >= 0) {
-                child_dev[i] = d->child[i];
-            } else {
-                child_dev[i] = -(int32_t)leaf_src.size() - 1;
-                leaf_src.push_back(i);
-            }
-        }
+        node_table(d->child, nn, child_dev, leaf_src);
         g->n_leaves = (int64_t)leaf_src.size();
-        build_ropes(d->child, nn, depth, order, leaf_src, rope_dev);
+        build_ropes(child_dev.data(), nn, depth, order, leaf_src, rope_dev);
         base_dev.resize((size_t)nb * nb * nb);
         for (int iz = 0; iz < nb; ++iz)
             for (int iy = 0; iy < nb; ++iy)
@@ -633,6 +661,27 @@ colt_status colt_release_grid(colt_grid g)
 }
 
 size_t colt_grid_bytes(colt_grid g) { return g ? g->mem.bytes : 0; }
+
+colt_status colt_octree_links(const int32_t *child, int64_t n_nodes, uint32_t *links,
+                              int64_t *n_leaves)
+{
+    if (!child || n_nodes <= 0 || !n_leaves)
+        return fail(COLT_ERR_ARG, "child, n_nodes > 0 and n_leaves are required");
+    if (n_nodes > INT32_MAX / 2) return fail(COLT_ERR_ARG, "too many octree nodes");
+    std::vector<int32_t> depth;
+    std::vector<int64_t> order;
+    const colt_status st = octree_walk(child, n_nodes, depth, order);
+    if (st != COLT_OK) return st;
+    std::vector<int32_t> child_dev;
+    std::vector<int64_t> leaf_src;
+    node_table(child, n_nodes, child_dev, leaf_src);
+    *n_leaves = (int64_t)leaf_src.size();
+    if (!links) return COLT_OK;
+    std::vector<uint32_t> rope;
+    build_ropes(child_dev.data(), n_nodes, depth, order, leaf_src, rope);
+    std::memcpy(links, rope.data(), rope.size() * sizeof(uint32_t));
+    return COLT_OK;
+}
 
 colt_status colt_grid_fields(colt_grid g, double *out)
 {
@@ -1025,7 +1074,7 @@ colt_status launch_shape(int prec, bool cams, std::vector<JobView> &views, uint6
 // next-event marches of every camera job, advance.
 hipError_t launch_sequence(int prec, bool cams, const LaunchView &L,
                            const std::vector<JobView> &views, int grid, int block,
-                           int march_min, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
+                           hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
     hipError_t e = launch_plan(L, false, s);
     if (e == hipSuccess && t0) e = hipEventRecord(t0, s);
@@ -1037,8 +1086,7 @@ hipError_t launch_sequence(int prec, bool cams, const LaunchView &L,
         int per_cu = 0;
         e = peel_occupancy(prec, views[j].g.kind, &per_cu);
         if (e == hipSuccess)
-            e = launch_peel(prec, views[j], L.peel_work + j, march_min,
-                            cu_count() * std::max(per_cu, 1), s);
+            e = launch_peel(prec, views[j], L.peel_work + j, cu_count() * std::max(per_cu, 1), s);
     }
     if (e == hipSuccess) e = launch_plan(L, true, s);
     return e;
@@ -1143,7 +1191,7 @@ colt_status transport_impl(const colt_job *jobs, int32_t n_jobs, const colt_laun
             HIP_TRY(hipEventCreate(&g_t0));
             HIP_TRY(hipEventCreate(&g_t1));
         }
-        HIP_TRY(launch_sequence(prec, cams, L, views, grid, block, L.march_min, s,
+        HIP_TRY(launch_sequence(prec, cams, L, views, grid, block, s,
                                 timed ? g_t0 : nullptr, timed ? g_t1 : nullptr));
         if (timed) g_timed = true;
         if (b) HIP_TRY(hipEventRecord(b->done, s));
@@ -1238,7 +1286,7 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
                                     stop_host);
     if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        const hipError_t e1 = launch_sequence(prec, cams, L, views, grid, block, L.march_min, s,
+        const hipError_t e1 = launch_sequence(prec, cams, L, views, grid, block, s,
                                               nullptr, nullptr);
         e = hipStreamEndCapture(s, &gr->graph);
         if (e1 != hipSuccess) e = e1;

@@ -211,20 +211,21 @@ __device__ __forceinline__ void snap_face(CellBox &c, double r[3], const double 
     }
 }
 
-// Octree crossing through the leaf's neighbour link: the node across the face
-// (same level, or the coarser leaf there), then a descent inside it only if it
-// is refined.  Where r lies on one of that node's other faces and k points out
-// of it, the tie rules of the search from the root could pick a diagonal
-// cell, so that case, and links the set-up could not encode, use the search.
-// Either way the cell is the one locate() finds.
+// Octree crossing through the leaf's neighbour link: the leaf across the face
+// (same level or coarser), read straight from the link, or the refined node
+// across at the leaf's level, which is descended.  Where r lies on one of that
+// cell's other faces and k points out of it, the tie rules of the search from
+// the root could pick a diagonal cell, so that case, and links the set-up could
+// not encode, use the search.  Either way the cell is the one locate() finds.
 __device__ __forceinline__ bool cross_octree(const GridView &g, CellBox &c, const double r[3],
                                              const double k[3], int axis, int step)
 {
     const uint32_t e = g.rope[(size_t)c.cell * 6 + 2 * axis + (step > 0 ? 1 : 0)];
     if (e == 0xFFFFFFFFu) return false;                  // the domain face
     if (e == 0xFFFFFFFEu) return locate(g, r, k, c);
-    const int up = (int)(e >> 27);
-    int node = (int)(e & 0x7FFFFFFu);
+    const bool leaf = (e >> 31) != 0u;
+    const int up = (int)((e >> 27) & 15u);
+    const int idx = (int)(e & 0x7FFFFFFu);
     const double size = c.size * (double)(1u << up);     // exact (powers of two)
     const double inv_size = 1.0 / size;                   // exact as well
     double lo[3];
@@ -247,7 +248,13 @@ __device__ __forceinline__ bool cross_octree(const GridView &g, CellBox &c, cons
         if (d2 >= g.esc_r * g.esc_r) return false;
     }
     c.lo[0] = lo[0]; c.lo[1] = lo[1]; c.lo[2] = lo[2];
+    if (leaf) {
+        c.size = size;
+        c.cell = idx;
+        return true;
+    }
     double sz = size;
+    int node = idx;
     int ch = g.child[node];
     while (ch >= 0) {
         const double half = 0.5 * sz;
@@ -461,6 +468,42 @@ __device__ __forceinline__ int pixel_of(const JobView &J, const double *cam, con
     }
     pu = pu / J.fov + 0.5;
     pv = pv / J.fov + 0.5;
+    if (!(pu >= 0.0 && pu < 1.0 && pv >= 0.0 && pv < 1.0)) return -1;
+    int iu = (int)(pu * J.npix), iv = (int)(pv * J.npix);
+    iu = (iu >= J.npix) ? J.npix - 1 : iu;
+    iv = (iv >= J.npix) ? J.npix - 1 : iv;
+    return iv * J.npix + iu;
+}
+
+// Camera spectrum bin and image pixel for the march kernel: the forms of
+// bin_of and pixel_of with their divisions replaced by products with
+// reciprocals taken once per launch (a bin or pixel can differ from the
+// quotient form only where a value lies within a rounding of an edge).
+struct BinPixScale {
+    double bin_lo, bin_scale, inv_fov;
+};
+
+__device__ __forceinline__ int bin_scaled(double x, const BinPixScale &q, int n)
+{
+    if (x < q.bin_lo) return 0;
+    const double t = (x - q.bin_lo) * q.bin_scale;
+    if (t >= n) return n + 1;
+    return 1 + (int)t;
+}
+
+__device__ __forceinline__ int pixel_scaled(const JobView &J, const BinPixScale &q,
+                                            const double *cam, const double r[3])
+{
+    if (J.npix <= 0) return -1;
+    double pu = 0.0, pv = 0.0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const double rc = r[e] - J.g.centre[e];
+        pu += rc * cam[6 + e];
+        pv += rc * cam[9 + e];
+    }
+    pu = pu * q.inv_fov + 0.5;
+    pv = pv * q.inv_fov + 0.5;
     if (!(pu >= 0.0 && pu < 1.0 && pv >= 0.0 && pv < 1.0)) return -1;
     int iu = (int)(pu * J.npix), iv = (int)(pv * J.npix);
     iu = (iu >= J.npix) ? J.npix - 1 : iu;
@@ -1472,28 +1515,35 @@ __global__ __launch_bounds__(256) void k_advance(LaunchView L)
 // Deferred next-event marches (Sec. 6.1): each task follows one camera's ray
 // from an event to the domain edge, adding the optical depth of every cell
 // (H I at the Doppler-shifted frequency of that cell, and dust), and tallies
-// W exp(-tau) unless the cut-off is passed first.  A lean persistent kernel:
-// lanes take tasks from the job's buffer (one atomic per wave) and step their
-// marches, the wave stepping on while a quarter of its lanes (at most
-// march_min) are still going, so one long march does not hold the wave.  The
-// first step repeats the event cell that the transport kernel already found
-// below the cut-off (it is not counted again).
+// W exp(-tau) unless the cut-off is passed first.  A lean persistent kernel in
+// which lanes step marches at every iteration: lanes whose marches end take
+// the next tasks they hold as soon as a few of them wait, so that this set-up
+// is shared by several lanes even where marches are long.  Next tasks are
+// loaded ahead, once a quarter of the wave needs one (or a lane would idle),
+// from a chunk of task slots the wave claims with one atomic; a chunk lies
+// inside one sub-buffer, so a lane's slot is the chunk start plus its rank.
+// The first step repeats the event cell that the transport kernel already
+// found below the cut-off (it is not counted again).
 // ---------------------------------------------------------------------------
+constexpr uint32_t kPeelChunk = 256;     // task slots a wave claims at a time
+constexpr int kPeelTake = 8;             // ended marches that start the next tasks
+
 template <typename R, int GK>
-__global__ __launch_bounds__(256, COLT_PEEL_MIN_BLOCKS) void k_peel(JobView J, unsigned long long *work,
-                                                                  int march_min)
+__global__ __launch_bounds__(256, COLT_PEEL_MIN_BLOCKS) void k_peel(JobView J, unsigned long long *work)
 {
     __shared__ double s_cam[12 * kMaxCams];
-    __shared__ uint32_t s_pre[kTaskSubs + 1];
+    // chunks before each sub-buffer's first, and its task count
+    __shared__ uint32_t s_chunk[kTaskSubs + 1], s_n[kTaskSubs];
     for (int i = threadIdx.x; i < 12 * J.n_cams; i += blockDim.x) s_cam[i] = J.cam[i];
     if (threadIdx.x == 0) {
         uint32_t acc = 0;
         for (int b = 0; b < kTaskSubs; ++b) {
-            s_pre[b] = acc;
             const uint32_t nb = J.ctl->tn[b * 16];
-            acc += (nb < J.task_sub_cap) ? nb : J.task_sub_cap;
+            s_n[b] = (nb < J.task_sub_cap) ? nb : J.task_sub_cap;
+            s_chunk[b] = acc;
+            acc += (s_n[b] + kPeelChunk - 1) / kPeelChunk;
         }
-        s_pre[kTaskSubs] = acc;
+        s_chunk[kTaskSubs] = acc;
     }
     __syncthreads();
     if constexpr (GK == 0) {
@@ -1504,90 +1554,125 @@ __global__ __launch_bounds__(256, COLT_PEEL_MIN_BLOCKS) void k_peel(JobView J, u
     }
     const int lane = threadIdx.x & 63;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t total = s_pre[kTaskSubs];
-    bool drained = total == 0, have = false, first = false;
+    const uint32_t n_chunks = s_chunk[kTaskSubs];
+    const BinPixScale q = {J.cam_xmin, (double)J.cam_nbins / (J.cam_xmax - J.cam_xmin),
+                           (J.npix > 0) ? 1.0 / J.fov : 0.0};
+    // the wave's claimed task slots [wlo, whi) (wave-uniform)
+    uint32_t wlo = 0, whi = 0;
+    bool drained = n_chunks == 0;
+    // the march being stepped
+    bool have = false, first = false;
     CellBox c;
     double r[3] = {0.0, 0.0, 0.0}, tau = 0.0;
     R xl = R(0), W = R(0);
     int cam = 0, bin = 0, pix = -1;
     unsigned long long id = 0, steps = 0;
+    // the next task, loaded ahead
+    bool nv = false;
+    double nr[3] = {0.0, 0.0, 0.0};
+    float nlo[3] = {0.0f, 0.0f, 0.0f}, nsize = 0.0f;
+    int32_t ncell = 0, ncam = -1;
+    R nxl = R(0), nW = R(0);
+    unsigned long long nid = 0;
     for (;;) {
+        // lanes whose marches have ended take the tasks they hold, once
+        // kPeelTake of them wait (or the wave has no march left)
+        const uint64_t ready = __ballot(!have && nv);
+        if (ready && (__popcll(ready) >= kPeelTake || !__any(have)) && !have && nv) {
+            r[0] = nr[0];
+            r[1] = nr[1];
+            r[2] = nr[2];
+            c.lo[0] = (double)nlo[0];
+            c.lo[1] = (double)nlo[1];
+            c.lo[2] = (double)nlo[2];
+            c.size = (double)nsize;
+            c.cell = ncell;
+            cam = ncam;
+            xl = nxl;
+            W = nW;
+            id = nid;
+            bin = bin_scaled((double)xl, q, J.cam_nbins);
+            pix = pixel_scaled(J, q, s_cam + 12 * cam, r);
+            tau = 0.0;
+            first = true;
+            have = true;
+            nv = false;
+        }
+        // lanes without a next task load one from the wave's chunk
         if (!drained) {
-            const uint64_t need = __ballot(!have);
-            if (need) {
-                const int n_need = __popcll(need);
-                const int leader = __ffsll((unsigned long long)need) - 1;
-                uint32_t base = 0;
-                if (lane == leader) base = (uint32_t)atomicAdd(work, (unsigned long long)n_need);
-                base = __shfl(base, leader);
-                if (base + (uint32_t)n_need >= total) drained = true;
-                const uint32_t w = base + (uint32_t)__popcll(need & lane_lt);
-                if (!have && w < total) {
-                    int b = 0;
+            const uint64_t need = __ballot(!nv);
+            if (__popcll(need) >= 16 || __ballot(!nv && !have)) {
+                if (wlo >= whi) {
+                    uint32_t k = 0;
+                    if (lane == 0) k = (uint32_t)atomicAdd(work, 1ull);
+                    k = __builtin_amdgcn_readfirstlane(k);
+                    if (k >= n_chunks) {
+                        drained = true;
+                    } else {
+                        int b = 0;
 #pragma unroll
-                    for (int h = kTaskSubs / 2; h > 0; h >>= 1)
-                        if (s_pre[b + h] <= w) b += h;
-                    const uint32_t t = (uint32_t)b * J.task_sub_cap + (w - s_pre[b]);
-                    cam = J.task.cam[t];
-                    if (cam >= 0 && cam < J.n_cams) {
-                        const TaskSoA &T = J.task;
-                        r[0] = T.rx[t];
-                        r[1] = T.ry[t];
-                        r[2] = T.rz[t];
-                        c.lo[0] = (double)T.lox[t];
-                        c.lo[1] = (double)T.loy[t];
-                        c.lo[2] = (double)T.loz[t];
-                        c.size = (double)T.size[t];
-                        c.cell = T.cell[t];
-                        xl = reinterpret_cast<const R *>(T.xl)[t];
-                        W = reinterpret_cast<const R *>(T.W)[t];
-                        id = T.id[t];
-                        bin = bin_of((double)xl, J.cam_xmin, J.cam_xmax, J.cam_nbins);
-                        pix = pixel_of(J, s_cam + 12 * cam, r);
-                        tau = 0.0;
-                        first = true;
-                        have = true;
+                        for (int h = kTaskSubs / 2; h > 0; h >>= 1)
+                            if (s_chunk[b + h] <= k) b += h;
+                        const uint32_t off = (k - s_chunk[b]) * kPeelChunk;
+                        const uint32_t n = (s_n[b] - off < kPeelChunk) ? s_n[b] - off : kPeelChunk;
+                        wlo = (uint32_t)b * J.task_sub_cap + off;
+                        whi = wlo + n;
                     }
+                }
+                if (!drained) {
+                    const uint32_t t = wlo + (uint32_t)__popcll(need & lane_lt);
+                    if (!nv && t < whi) {
+                        const TaskSoA &T = J.task;
+                        ncam = T.cam[t];
+                        nr[0] = T.rx[t];
+                        nr[1] = T.ry[t];
+                        nr[2] = T.rz[t];
+                        nlo[0] = T.lox[t];
+                        nlo[1] = T.loy[t];
+                        nlo[2] = T.loz[t];
+                        nsize = T.size[t];
+                        ncell = T.cell[t];
+                        nxl = reinterpret_cast<const R *>(T.xl)[t];
+                        nW = reinterpret_cast<const R *>(T.W)[t];
+                        nid = T.id[t];
+                        // empty slots (cam = -1) are skipped
+                        nv = ncam >= 0 && ncam < J.n_cams;
+                    }
+                    const uint32_t took = (uint32_t)__popcll(need);
+                    wlo = (wlo + took < whi) ? wlo + took : whi;
                 }
             }
         }
-        if (!__any(have)) {
+        if (!__any(have || nv)) {
             if (drained) break;
             continue;
         }
-        const int going0 = __popcll(__ballot(have));
-        const int quarter = (going0 + 3) >> 2;
-        const int stop_below = drained ? 1 : ((march_min < quarter) ? march_min : quarter);
-        for (;;) {
-            if (have) {
-                const double *cm = s_cam + 12 * cam;
-                const double d[3] = {cm[0], cm[1], cm[2]};
-                const double idv[3] = {cm[3], cm[4], cm[5]};
-                const R dr[3] = {(R)cm[0], (R)cm[1], (R)cm[2]};
-                const CellRec<R> cr = load_cell<R>(J.g, c.cell);
-                double l;
-                int axis;
-                bool by_sphere;
-                tau += peel_cell_tau<R>(J, c, cr, r, d, idv, dr, xl, l, axis, by_sphere);
-                if (!first) ++steps;
-                first = false;
-                int st = 0;
-                if (tau > J.tau_peel_max) {
-                    st = 2;
-                } else if (by_sphere) {
-                    st = 1;
-                } else {
+        if (have) {
+            const double *cm = s_cam + 12 * cam;
+            const double d[3] = {cm[0], cm[1], cm[2]};
+            const double idv[3] = {cm[3], cm[4], cm[5]};
+            const R dr[3] = {(R)cm[0], (R)cm[1], (R)cm[2]};
+            const CellRec<R> cr = load_cell<R>(J.g, c.cell);
+            double l;
+            int axis;
+            bool by_sphere;
+            tau += peel_cell_tau<R>(J, c, cr, r, d, idv, dr, xl, l, axis, by_sphere);
+            if (!first) ++steps;
+            first = false;
+            int st = 0;
+            if (tau > J.tau_peel_max) {
+                st = 2;
+            } else if (by_sphere) {
+                st = 1;
+            } else {
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) r[e] += l * d[e];
-                    if (!cross(J.g, c, r, d, axis)) st = 1;
-                }
-                if (st) {
-                    have = false;
-                    if (st == 1) peel_tally(J, cam, bin, pix, id, (double)W * ::exp(-tau));
-                }
+                for (int e = 0; e < 3; ++e) r[e] += l * d[e];
+                if (!cross(J.g, c, r, d, axis)) st = 1;
             }
-            const int going = __popcll(__ballot(have));
-            if (going == 0 || going < stop_below) break;
+            if (st) {
+                have = false;
+                if (st == 1) peel_tally(J, cam, bin, pix, id, (double)W * ::exp(-tau));
+            }
         }
     }
     // crossings of the marches beyond the event cell, one atomic per wave
@@ -1877,21 +1962,20 @@ hipError_t launch_plan(const LaunchView &L, bool advance, hipStream_t s)
 }
 
 template <typename R, int GK>
-static hipError_t peel_t(const JobView &J, unsigned long long *work, int march_min, int grid,
-                         hipStream_t s)
+static hipError_t peel_t(const JobView &J, unsigned long long *work, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_peel<R, GK>), dim3(grid), dim3(256), 0, s, J, work, march_min);
+    hipLaunchKernelGGL((k_peel<R, GK>), dim3(grid), dim3(256), 0, s, J, work);
     return hipGetLastError();
 }
 
-hipError_t launch_peel(int precision, const JobView &J, unsigned long long *work, int march_min,
-                       int grid, hipStream_t s)
+hipError_t launch_peel(int precision, const JobView &J, unsigned long long *work, int grid,
+                       hipStream_t s)
 {
     if (precision == 0)
-        return J.g.kind == 0 ? peel_t<double, 0>(J, work, march_min, grid, s)
-                             : peel_t<double, 1>(J, work, march_min, grid, s);
-    return J.g.kind == 0 ? peel_t<float, 0>(J, work, march_min, grid, s)
-                         : peel_t<float, 1>(J, work, march_min, grid, s);
+        return J.g.kind == 0 ? peel_t<double, 0>(J, work, grid, s)
+                             : peel_t<double, 1>(J, work, grid, s);
+    return J.g.kind == 0 ? peel_t<float, 0>(J, work, grid, s)
+                         : peel_t<float, 1>(J, work, grid, s);
 }
 
 hipError_t peel_occupancy(int precision, int grid_kind, int *blocks_per_cu)

@@ -19,8 +19,8 @@ hipError_t transport_occupancy(int precision, bool cams, bool single, int grid_k
                                int *blocks_per_cu);
 // k_plan (advance = false) before a transport launch, k_advance after it
 hipError_t launch_plan(const LaunchView &L, bool advance, hipStream_t s);
-hipError_t launch_peel(int precision, const JobView &J, unsigned long long *work, int march_min,
-                       int grid, hipStream_t s);
+hipError_t launch_peel(int precision, const JobView &J, unsigned long long *work, int grid,
+                       hipStream_t s);
 hipError_t peel_occupancy(int precision, int grid_kind, int *blocks_per_cu);
 // The current device's fixed launch table for colt_transport_static (its
 // address found once per device) and the kernel that writes job views into it.
