@@ -7,7 +7,10 @@ albedo 0.32, global core-skipping from a*tau0 = 4702, anisotropic scattering,
 transports one full job (fresh seed) with the gas already resident in HBM and
 reads its tallies back.  Consecutive steps are queued on four streams in turn
 (--streams), so the long-lived last photons of one step share the device with
-the bulk of the next; all steps complete inside the timed region.  The
+the bulk of the next (optionally, with --tail-live and --launches, waves left
+with few live photons once a step's photons are all handed out pass them on
+to the step's next launch, packed into full waves).  All steps complete
+inside the timed region.  The
 headline value is in FP32-bulk mode (FP32 Voigt/sampling/directions, FP64
 position, optical depth and tallies); the same steps in all-FP64 mode are
 reported beside it.  The roofline figures use the transport kernel's own
@@ -311,7 +314,7 @@ def full_histories_section(n_photons):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--photons", type=int, default=1_000_000)
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison")
@@ -320,6 +323,12 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--streams", type=int, default=4,
                     help="streams the steps are queued on in turn (1: one step at a time)")
+    ap.add_argument("--tail-live", type=int, default=0,
+                    help="pipelined steps: once a step's photons are all handed out, waves "
+                         "with fewer live photons hand them to the next of its launches "
+                         "(0: off, the default: measured slower on this workload)")
+    ap.add_argument("--launches", type=int, default=1,
+                    help="launch sequences queued per pipelined step")
     ap.add_argument("--batch", type=int, default=4,
                     help="jobs of the workload fused in one launch for the batched figure "
                          "(0 or 1 skips it)")
@@ -387,10 +396,17 @@ def main():
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(st)
             colt.transport([j], block=args.block, blocks_per_cu=args.blocks_per_cu,
-                           stream=ctypes.c_void_p(st.cuda_stream))
+                           stream=ctypes.c_void_p(st.cuda_stream), tail_live=args.tail_live,
+                           launches=args.launches)
             e1.record(st)
             marks.append((e0, e1))
-        counters = [j.tally(wait=True)["counters"] for j in jobs]
+        counters = []
+        for i, j in enumerate(jobs):
+            j.tally(wait=True)
+            if not j.complete:      # the tail needed more launches than were queued
+                colt.transport_all([j], tail_live=args.tail_live,
+                                   stream=ctypes.c_void_p(sts[i % len(sts)].cuda_stream))
+            counters.append(j.tally(wait=True)["counters"])
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         kern = [e0.elapsed_time(e1) for e0, e1 in marks]
@@ -445,7 +461,7 @@ def main():
                    "core_skip": "global x_crit(a tau0=4702)=3.35", "photons_per_step": args.photons,
                    "spectrum_bins": 500, "precision": "FP32-bulk"},
         "photons_per_s": photons / el,
-        "streams": args.streams,
+        "streams": args.streams, "tail_live": args.tail_live, "launches_per_step": args.launches,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "of": "one step alone, launch to tallies on the host"},
         "per_step": {"scatterings": scat / args.steps,

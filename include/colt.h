@@ -174,6 +174,20 @@ typedef struct {
                                           /* within its pass                       */
     int32_t stop_token;                   /* 1..63: the launch stops when          */
                                           /* colt_stop_set(token, 1); 0 = none     */
+    int32_t tail_live;                    /* 0 = off; 1..64: once a launch has     */
+                                          /* handed out all its photons, a wave    */
+                                          /* with fewer live photons suspends them */
+                                          /* and exits, so the last long histories */
+                                          /* of a job do not hold the device; a    */
+                                          /* later launch resumes them in full     */
+                                          /* waves.  A launch that starts with     */
+                                          /* fewer than 16384 photons runs to the  */
+                                          /* end.                                  */
+    int32_t launches;                     /* launch sequences the call enqueues    */
+                                          /* (0 = 1), each planned on the device   */
+                                          /* from the jobs' control blocks; one    */
+                                          /* that finds nothing left returns at    */
+                                          /* once                                  */
 } colt_launch;
 
 typedef struct {
@@ -234,9 +248,9 @@ colt_status colt_emit(colt_grid grid, const colt_source_desc *src,
  * 0); lanes that finish a photon take the next one from a shared queue, so
  * jobs of uneven cost share the device.  The launch is planned on the device
  * from each job's control block.  A launch may stop early (stop_token, or a
- * camera job's task buffer near full): its photons in flight are suspended and
- * colt_job_status reports the job unfinished until a later launch completes
- * it.  A launch that can stop, and any launch of a job a stopped launch may
+ * camera job's task buffer near full, or tail_live): its photons in flight are
+ * suspended and colt_job_status reports the job unfinished until a later
+ * launch completes it.  A launch that can stop, and any launch of a job a stopped launch may
  * have left unfinished, waits for the job's launches on other streams.  `jobs`
  * is borrowed for the call.  Errors: COLT_ERR_ARG (list, block, token or a
  * task buffer too small for one wave), COLT_ERR_NOMEM (launch table),

@@ -73,7 +73,8 @@ class JobParams(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("photons_per_job", ctypes.c_uint64), ("time_kernel", ctypes.c_int32),
-                ("march_min", ctypes.c_int32), ("stop_token", ctypes.c_int32)]
+                ("march_min", ctypes.c_int32), ("stop_token", ctypes.c_int32),
+                ("tail_live", ctypes.c_int32), ("launches", ctypes.c_int32)]
 
 
 class TallyOut(ctypes.Structure):
@@ -398,14 +399,15 @@ class Job:
 
 
 def transport(jobs, block=0, blocks_per_cu=0, photons_per_job=0, time_kernel=False,
-              stream=None, march_min=0, stop_token=0):
-    """Runs (the next slice of) each job's photons in one persistent launch per
-    precision on the stream (asynchronous).  The launch may stop early (a stop
-    token, or a camera job's task buffer): then call again until complete."""
+              stream=None, march_min=0, stop_token=0, tail_live=0, launches=1):
+    """Runs (the next slice of) each job's photons in `launches` persistent
+    launch sequences per precision on the stream (asynchronous).  A launch may
+    stop early (a stop token, a camera job's task buffer, or tail_live): then
+    call again until complete."""
     jobs = list(jobs)
     arr = (ctypes.c_void_p * max(len(jobs), 1))(*[j.handle for j in jobs])
     lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), int(bool(time_kernel)),
-                int(march_min), int(stop_token))
+                int(march_min), int(stop_token), int(tail_live), int(launches))
     _check(lib().colt_transport(arr, len(jobs), ctypes.byref(lc),
                                 stream if stream is not None else current_stream()))
 
@@ -415,13 +417,13 @@ class Graph:
     launch() replays an epoch of up to photons_per_job photons per job."""
 
     def __init__(self, jobs, photons_per_job=0, block=0, blocks_per_cu=0, march_min=0,
-                 stop_token=0):
+                 stop_token=0, tail_live=0, launches=1):
         torch = _torch()
         self.jobs = list(jobs)
         self._capture = torch.cuda.Stream()
         arr = (ctypes.c_void_p * len(self.jobs))(*[j.handle for j in self.jobs])
         lc = Launch(int(block), int(blocks_per_cu), int(photons_per_job), 0, int(march_min),
-                    int(stop_token))
+                    int(stop_token), int(tail_live), int(launches))
         h = ctypes.c_void_p()
         torch.cuda.current_stream().synchronize()
         _check(lib().colt_graph_create(arr, len(self.jobs), ctypes.byref(lc),

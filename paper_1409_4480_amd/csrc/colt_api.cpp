@@ -1014,7 +1014,7 @@ TableLayout table_layout(int nj)
 }
 
 LaunchView table_view(char *dev, const TableLayout &t, int nj, uint64_t quota, int march_min,
-                      const int *stop_host)
+                      const int *stop_host, int tail_live)
 {
     LaunchView L{};
     L.jobs = (JobView *)(dev + t.jobs);
@@ -1029,6 +1029,7 @@ LaunchView table_view(char *dev, const TableLayout &t, int nj, uint64_t quota, i
     L.quota = quota;
     L.n_jobs = nj;
     L.march_min = march_min;
+    L.tail_live = tail_live;
     return L;
 }
 
@@ -1112,6 +1113,10 @@ colt_status transport_impl(const colt_job *jobs, int32_t n_jobs, const colt_laun
     bool timed = launch && launch->time_kernel;
     const int token = launch ? launch->stop_token : 0;
     if (token < 0 || token >= kStopTokens) return fail(COLT_ERR_ARG, "stop token 0..%d", kStopTokens - 1);
+    const int tail_live = launch ? launch->tail_live : 0;
+    if (tail_live < 0 || tail_live > 64) return fail(COLT_ERR_ARG, "tail_live must lie in 0..64");
+    const int reps = (launch && launch->launches > 0) ? launch->launches : 1;
+    if (launch && launch->launches < 0) return fail(COLT_ERR_ARG, "launches must not be negative");
     const int *stop_host = nullptr;
     if (token) {
         if (fixed) {
@@ -1147,7 +1152,7 @@ colt_status transport_impl(const colt_job *jobs, int32_t n_jobs, const colt_laun
         }
         if (members.empty()) continue;
         const int nj = (int)members.size();
-        const bool may_stop = token != 0 || cams;
+        const bool may_stop = token != 0 || cams || tail_live > 0;
         // a launch that may stop, or a job another such launch may have left
         // suspended photons to, must follow the job's launches on other streams
         for (colt_job j : members) {
@@ -1185,14 +1190,18 @@ colt_status transport_impl(const colt_job *jobs, int32_t n_jobs, const colt_laun
             HIP_TRY(hipMemcpyAsync(b->dev, b->host, t.bytes, hipMemcpyHostToDevice, s));
             table = (char *)b->dev;
         }
-        const LaunchView L = table_view(table, t, nj, quota, march_min_of(launch, prec), stop_host);
+        const LaunchView L = table_view(table, t, nj, quota, march_min_of(launch, prec), stop_host,
+                                        tail_live);
         if (fixed) timed = false;
         if (timed && !g_t0) {
             HIP_TRY(hipEventCreate(&g_t0));
             HIP_TRY(hipEventCreate(&g_t1));
         }
-        HIP_TRY(launch_sequence(prec, cams, L, views, grid, block, s,
-                                timed ? g_t0 : nullptr, timed ? g_t1 : nullptr));
+        // the timing events bracket the first to the last transport kernel
+        for (int rep = 0; rep < reps; ++rep)
+            HIP_TRY(launch_sequence(prec, cams, L, views, grid, block, s,
+                                    (timed && rep == 0) ? g_t0 : nullptr,
+                                    (timed && rep == reps - 1) ? g_t1 : nullptr));
         if (timed) g_timed = true;
         if (b) HIP_TRY(hipEventRecord(b->done, s));
         for (colt_job j : members) {
@@ -1251,6 +1260,10 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
     if (block < 64 || block > 256 || block % 64) return fail(COLT_ERR_ARG, "block 64..256");
     const int token = launch ? launch->stop_token : 0;
     if (token < 0 || token >= kStopTokens) return fail(COLT_ERR_ARG, "stop token 0..%d", kStopTokens - 1);
+    const int tail_live = launch ? launch->tail_live : 0;
+    if (tail_live < 0 || tail_live > 64) return fail(COLT_ERR_ARG, "tail_live must lie in 0..64");
+    if (launch && launch->launches < 0) return fail(COLT_ERR_ARG, "launches must not be negative");
+    const int reps = (launch && launch->launches > 0) ? launch->launches : 1;
     const int *stop_host = nullptr;
     if (token) {
         int *w = stop_words();
@@ -1271,7 +1284,7 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
     colt_graph gr = new colt_graph_s();
     gr->jobs.assign(jobs, jobs + nj);
     gr->quota = launch ? launch->photons_per_job : 0;
-    gr->may_stop = token != 0 || cams;
+    gr->may_stop = token != 0 || cams || tail_live > 0;
     gr->alloc = jobs[0]->mem.alloc;
     gr->custom = jobs[0]->mem.custom;
     gr->dev = dev_alloc(gr->alloc, gr->custom, t.bytes);
@@ -1283,11 +1296,12 @@ colt_status colt_graph_create(const colt_job *jobs, int32_t n_jobs, const colt_l
     hipError_t e = hipMemcpyAsync(gr->dev, h.data(), t.bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     const LaunchView L = table_view((char *)gr->dev, t, nj, gr->quota, march_min_of(launch, prec),
-                                    stop_host);
+                                    stop_host, tail_live);
     if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        const hipError_t e1 = launch_sequence(prec, cams, L, views, grid, block, s,
-                                              nullptr, nullptr);
+        hipError_t e1 = hipSuccess;
+        for (int rep = 0; rep < reps && e1 == hipSuccess; ++rep)
+            e1 = launch_sequence(prec, cams, L, views, grid, block, s, nullptr, nullptr);
         e = hipStreamEndCapture(s, &gr->graph);
         if (e1 != hipSuccess) e = e1;
     }

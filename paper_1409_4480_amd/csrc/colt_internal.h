@@ -159,6 +159,11 @@ struct LaunchView {
     uint64_t quota;             // new photons per job (0: all that remain)
     int32_t n_jobs;
     int32_t march_min;          // a wave keeps stepping while this many lanes are in flight
+    int32_t tail_live;          // > 0: drained waves with fewer live photons suspend them
 };
+
+// A launch that starts with fewer photons (new and resumed) than this runs to
+// the end whatever tail_live asks, so repeated launches always finish a job.
+constexpr uint64_t kTailMinWork = 16384;
 
 }  // namespace colt

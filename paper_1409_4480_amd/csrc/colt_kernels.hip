@@ -1223,6 +1223,10 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
     const int march_min = L.march_min;
     bool res_left = rtotal > 0, new_left = total > 0;
     bool have = false, moving = false, stopping = false;   // stopping: a stop was seen
+    // the tail rule: with every photon handed out, a wave holding fewer than
+    // tail_live photons suspends them for a later launch (not in a launch
+    // that started small, which therefore always runs to the end)
+    const int tail_live = (total + rtotal >= kTailMinWork) ? L.tail_live : 0;
     uint32_t pass = 0;
     for (;;) {
         // a stop request set before or during this pass is acted on at its end;
@@ -1396,6 +1400,10 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
             break;
         }
         if (!any_have && !res_left && !new_left) break;
+        if (tail_live > 0 && !res_left && !new_left && __popcll(__ballot(have)) < tail_live) {
+            stopping = true;
+            break;
+        }
     }
     if (stopping) {
         // suspend the wave's photons (all in flight at the end of a pass) and

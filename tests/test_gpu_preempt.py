@@ -184,3 +184,39 @@ def test_jeans_core_skipping_matches_the_oracle():
     wl0 = dict(wl, params=dict(wl["params"], xcrit_mode=0))
     r0 = oracle.run(wl0["grid"], wl0["source"], wl0["params"], records=True)
     assert gout["counters"]["scat_hi"] < r0["counters"]["scat_hi"]
+
+
+@pytest.mark.parametrize("case", ["fp64", "fp32", "fp32_cams"])
+def test_tail_rule_gives_the_same_results(case):
+    """tail_live = 16: once the photons are all handed out, waves holding
+    fewer than 16 suspend them and the next launch resumes them in full waves.
+    The first launch leaves photons suspended, later ones (queued by one call,
+    then as many as needed) finish the job, and the records and tallies equal
+    a run in one launch; a launch that starts with fewer than 16384 photons
+    runs to the end (unless, with cameras, its task buffer fills)."""
+    prec = colt.FP64 if case == "fp64" else colt.FP32_BULK
+    cams = inputs.AXIS_CAMERAS if case == "fp32_cams" else None
+    wl = inputs.static_sphere(n=16, tau0=1e5, n_photons=40000, seed=35, isotropic=False,
+                              recoil=True, cameras=cams, cam_nbins=50, cam_npix=8)
+    say(f"[gpu] tail rule, {case}")
+    ref = colt.run(wl, precision=prec, record=True)
+    g = colt.Grid(wl["grid"])
+    j = colt.Job(g, wl["source"], wl["params"], precision=prec, record=True)
+    small = colt.Job(g, wl["source"], dict(wl["params"], n_photons=16383), precision=prec)
+    try:
+        colt.transport([j], tail_live=16)
+        nxt, n_susp, _ = j.pending()
+        say(f"    after one launch: next id {nxt}, {n_susp} suspended")
+        assert nxt == wl["params"]["n_photons"] and n_susp > 0
+        colt.transport([j], tail_live=16, launches=3)
+        n = colt.transport_all([j], tail_live=16)
+        say(f"    then {n} more call(s)")
+        out = j.tally()
+        if cams is None:
+            colt.transport([small], tail_live=16)
+            assert small.complete
+    finally:
+        j.release()
+        small.release()
+        g.release()
+    same_results(ref, out, tally_rtol=1e-12)
