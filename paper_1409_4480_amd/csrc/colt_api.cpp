@@ -533,7 +533,11 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
     void *stage = g->mem.get(raw.size() * sizeof(double));
     void *rd = g->mem.get((size_t)nl * sizeof(CellRec<double>));
     void *ad = g->mem.get((size_t)nl * sizeof(CellAux<double>));
-    void *rf = g->mem.get((size_t)nl * sizeof(CellRec<float>));
+    // FP32 octree records share a 64-byte line with the leaf's six links, so a
+    // crossing reads one line for the leaf it leaves and the leaf it enters
+    const int rf_stride = (d->kind == 1) ? 2 : 1;
+    static_assert(sizeof(CellRec<float>) == 32, "an FP32 record is half a 64-byte line");
+    void *rf = g->mem.get((size_t)nl * rf_stride * sizeof(CellRec<float>));
     void *af = g->mem.get((size_t)nl * sizeof(CellAux<float>));
     g->n_dev = (double *)g->mem.get((size_t)nl * sizeof(double));
     void *dchild = nullptr, *dbase = nullptr, *drope = nullptr;
@@ -564,7 +568,11 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
     const double *sd = (const double *)stage;
     if (e == hipSuccess)
         e = launch_cell_setup(nl, sd, sd + nl, sd + 4 * nl, sd + 2 * nl, sd + 3 * nl, g->dx_cm,
-                              rd, ad, rf, af, s);
+                              rd, ad, rf, rf_stride, af, s);
+    if (e == hipSuccess && d->kind == 1 && nl > 0)
+        e = hipMemcpy2DAsync((char *)rf + sizeof(CellRec<float>), 2 * sizeof(CellRec<float>),
+                             rope_dev.data(), 6 * sizeof(uint32_t), 6 * sizeof(uint32_t),
+                             (size_t)nl, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(g->n_dev, sd, (size_t)nl * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -580,6 +588,8 @@ colt_status colt_init_grid(const colt_grid_desc *d, const colt_allocator *alloc,
 
     GridView &v = g->view;
     v.kind = d->kind;
+    v.rec_stride = 1;          // the FP64 records and the separate link table
+    v.rope_stride = 6;
     v.cells = rd;
     v.aux = ad;
     v.child = (const int32_t *)dchild;
@@ -783,7 +793,15 @@ colt_status colt_emit(colt_grid g, const colt_source_desc *src, const colt_job_p
     const size_t ncs = (size_t)nc * p->cam_nbins, nimg = (size_t)nc * p->cam_npix * p->cam_npix;
     JobView &v = j->view;
     v.g = g->view;
-    if (p->precision == COLT_FP32_BULK) { v.g.cells = g->rec_f; v.g.aux = g->aux_f; }
+    if (p->precision == COLT_FP32_BULK) {
+        v.g.cells = g->rec_f;
+        v.g.aux = g->aux_f;
+        if (g->kind == 1) {
+            v.g.rec_stride = 2;
+            v.g.rope = (const uint32_t *)((const char *)g->rec_f + sizeof(CellRec<float>));
+            v.g.rope_stride = 16;
+        }
+    }
     v.src_kind = src->kind;
     v.n_src = src->n_src;
     v.freq_mode = src->freq_mode;

@@ -91,11 +91,14 @@ struct TaskSoA {
 struct GridView {
     int32_t kind;              // 0 Cartesian, 1 octree
     int32_t n[3];              // Cartesian cells per axis / octree base cells per axis
-    const void *cells;         // CellRec<R>[n_cells] (leaf order for octrees)
+    int32_t rec_stride;        // cell records between consecutive cells (2: FP32 octree,
+                               // whose leaf's links fill the second half of its 64-byte line)
+    int32_t rope_stride;       // uint32 words between consecutive leaves' links (6 or 16)
+    const void *cells;         // CellRec<R>[n_cells * rec_stride] (leaf order for octrees)
     const void *aux;           // CellAux<R>[n_cells]
     const int32_t *child;      // octree: >= 0 first child, < 0 -(leaf + 1)
     const int32_t *base;       // octree: node at the base level per base cell
-    const uint32_t *rope;      // octree: per leaf and face, the node across (see cross())
+    const uint32_t *rope;      // octree: per leaf and face, the leaf or node across (cross())
     double centre[3];          // box centre
     double esc_r;              // escape sphere radius (0 = box faces)
     double albedo;             // dust scattering probability per dust event

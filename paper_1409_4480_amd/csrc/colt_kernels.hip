@@ -47,7 +47,8 @@ __global__ void k_cell_setup(int64_t n, const double *__restrict__ n_HI,
                              const double *__restrict__ k_dust,
                              const double *__restrict__ atau_nl, double dx_cm,
                              CellRec<double> *__restrict__ rd, CellAux<double> *__restrict__ ad,
-                             CellRec<float> *__restrict__ rf, CellAux<float> *__restrict__ af)
+                             CellRec<float> *__restrict__ rf, int rf_stride,
+                             CellAux<float> *__restrict__ af)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -81,7 +82,7 @@ __global__ void k_cell_setup(int64_t n, const double *__restrict__ n_HI,
     CellRec<float> cf;
     cf.k0 = (float)c.k0; cf.a = (float)c.a; cf.s = (float)c.s; cf.kd = (float)c.kd;
     cf.ux = (float)c.ux; cf.uy = (float)c.uy; cf.uz = (float)c.uz; cf.xcw = (float)c.xcw;
-    rf[i] = cf;
+    rf[i * rf_stride] = cf;
     CellAux<float> xf;
     xf.g = (float)x.g;
     xf.atau_nl = (float)x.atau_nl;
@@ -220,7 +221,7 @@ __device__ __forceinline__ void snap_face(CellBox &c, double r[3], const double 
 __device__ __forceinline__ bool cross_octree(const GridView &g, CellBox &c, const double r[3],
                                              const double k[3], int axis, int step)
 {
-    const uint32_t e = g.rope[(size_t)c.cell * 6 + 2 * axis + (step > 0 ? 1 : 0)];
+    const uint32_t e = g.rope[(size_t)c.cell * g.rope_stride + 2 * axis + (step > 0 ? 1 : 0)];
     if (e == 0xFFFFFFFFu) return false;                  // the domain face
     if (e == 0xFFFFFFFEu) return locate(g, r, k, c);
     const bool leaf = (e >> 31) != 0u;
@@ -313,7 +314,7 @@ __device__ __forceinline__ double min_face_distance(const CellBox &c, const doub
 template <typename R>
 __device__ __forceinline__ CellRec<R> load_cell(const GridView &g, int32_t i)
 {
-    return reinterpret_cast<const CellRec<R> *>(g.cells)[i];
+    return reinterpret_cast<const CellRec<R> *>(g.cells)[(size_t)i * g.rec_stride];
 }
 
 template <typename R>
@@ -1213,8 +1214,11 @@ __global__ __launch_bounds__(256, (transport_min_blocks<R, CAMS>())) void k_tran
     if constexpr (GK == 0) {
         Jk.g.kind = 0;
         Jk.g.rope = nullptr;
+        Jk.g.rec_stride = 1;
     } else if constexpr (GK == 1) {
         Jk.g.kind = 1;
+        Jk.g.rec_stride = (sizeof(R) == 4) ? 2 : 1;
+        Jk.g.rope_stride = (sizeof(R) == 4) ? 16 : 6;
     }
     const JobView *const J_single = (sizeof(R) == 4) ? &Jk : L.jobs;
     const JobView *J = SINGLE ? J_single : nullptr;
@@ -1557,8 +1561,11 @@ __global__ __launch_bounds__(256, COLT_PEEL_MIN_BLOCKS) void k_peel(JobView J, u
     if constexpr (GK == 0) {
         J.g.kind = 0;
         J.g.rope = nullptr;
+        J.g.rec_stride = 1;
     } else if constexpr (GK == 1) {
         J.g.kind = 1;
+        J.g.rec_stride = (sizeof(R) == 4) ? 2 : 1;
+        J.g.rope_stride = (sizeof(R) == 4) ? 16 : 6;
     }
     const int lane = threadIdx.x & 63;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -1897,14 +1904,14 @@ hipError_t put_views(const JobView *views, int n, JobView *dst, hipStream_t s)
 // ---------------------------------------------------------------------------
 hipError_t launch_cell_setup(int64_t n, const double *n_HI, const double *T, const double *v,
                              const double *k_dust, const double *atau_nl, double dx_cm,
-                             void *rd, void *ad, void *rf, void *af, hipStream_t s)
+                             void *rd, void *ad, void *rf, int rf_stride, void *af, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const int block = 256;
     const int64_t grid = (n + block - 1) / block;
     hipLaunchKernelGGL(k_cell_setup, dim3((unsigned)grid), dim3(block), 0, s, n, n_HI, T, v,
                        k_dust, atau_nl, dx_cm, (CellRec<double> *)rd, (CellAux<double> *)ad,
-                       (CellRec<float> *)rf, (CellAux<float> *)af);
+                       (CellRec<float> *)rf, rf_stride, (CellAux<float> *)af);
     return hipGetLastError();
 }
 

@@ -8,9 +8,10 @@
 
 namespace colt {
 
+// rf_stride: CellRec<float> slots per cell (2 for octrees: links in the second half)
 hipError_t launch_cell_setup(int64_t n, const double *n_HI, const double *T, const double *v,
                              const double *k_dust, const double *atau_nl, double dx_cm,
-                             void *rd, void *ad, void *rf, void *af, hipStream_t s);
+                             void *rd, void *ad, void *rf, int rf_stride, void *af, hipStream_t s);
 // J1: the job of a one-job launch (L.n_jobs == 1), passed to the kernel by value
 hipError_t launch_transport(int precision, bool cams, const LaunchView &L, const JobView &J1,
                             int grid, int block, hipStream_t s);

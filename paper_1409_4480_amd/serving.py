@@ -34,8 +34,9 @@ def footprint(wl, record=False, precision=colt.FP32_BULK):
     g = wl["grid"]
     n_cells = int(np.asarray(g["n_HI"]).size)
     n = CELL_BYTES * n_cells
-    if g.get("child") is not None:                     # child table, base table,
-        n += (4 + 24) * n_cells + 4 * 128 ** 3          # six neighbour links per leaf
+    if g.get("child") is not None:                     # child table, base table, six
+        n += (4 + 24 + 32) * n_cells + 4 * 128 ** 3     # links per leaf (again beside the
+                                                        # FP32 record, filling its line)
     n += colt.job_footprint(wl["source"], wl["params"], precision, record)
     return n + (64 << 10)
 
