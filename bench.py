@@ -5,9 +5,10 @@ centre radial optical depth tau0 = 1e7 at T = 1e4 K, grey dust tau_d = 1 with
 albedo 0.32, global core-skipping from a*tau0 = 4702, anisotropic scattering,
 500-bin escape spectrum, 1e6 photons from a central point source.  Each step
 transports one full job (fresh seed) with the gas already resident in HBM and
-reads its tallies back.  Consecutive steps are queued on four streams in turn
-(--streams), so the long-lived last photons of one step share the device with
-the bulk of the next (optionally, with --tail-live and --launches, waves left
+reads its tallies back.  Consecutive steps are queued on eight streams in turn
+(--streams), each launched on half of the device's workgroup slots
+(--pipe-blocks-per-cu 2), so two or more steps run side by side and the
+long-lived last photons of one step share the device with the bulk of the next (optionally, with --tail-live and --launches, waves left
 with few live photons once a step's photons are all handed out pass them on
 to the step's next launch, packed into full waves).  All steps complete
 inside the timed region.  The
@@ -215,17 +216,51 @@ def precision_errors(grid, wl):
     return res
 
 
-def timed_job(grid, wl, precision, cap=0):
+PROGRESS_TOKEN = 9
+
+
+def timed_job(grid, wl, precision, cap=0, progress=None):
     """Runs one job to completion (as many launches as its next-event task
     buffer needs) and returns its counters, the wall time between device
-    synchronisations and the launch count."""
+    synchronisations and the launch count.  With `progress` (a name), a host
+    thread also sets a stop word every 20 s, so no launch runs longer than
+    that (the stopped photons resume exactly in the next launch), and a
+    progress line is printed between launches."""
+    import threading
+
     import torch
 
     from paper_1409_4480_amd import colt
     job = colt.Job(grid, wl["source"], wl["params"], precision=precision, max_events=cap)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    n = colt.transport_all([job])
+    if progress is None:
+        n = colt.transport_all([job])
+    else:
+        done = threading.Event()
+
+        def tick():
+            while not done.wait(20.0):
+                colt.stop_set(PROGRESS_TOKEN, True)
+        th = threading.Thread(target=tick, daemon=True)
+        th.start()
+        n, last = 0, t
+        try:
+            while not job.complete:
+                colt.stop_set(PROGRESS_TOKEN, False)
+                colt.transport([job], stop_token=PROGRESS_TOKEN)
+                n += 1
+                job.tally(wait=True)
+                now = time.perf_counter()
+                if now - last > 15.0:
+                    nxt, n_susp, _ = job.pending()
+                    print(f"#   {progress}: {now - t:.0f} s, {n} launches, {nxt} photons "
+                          f"started, {n_susp} in flight", file=sys.stderr, flush=True)
+                    last = now
+        finally:
+            done.set()
+            th.join()
+            colt.stop_set(PROGRESS_TOKEN, False)
     c = job.tally(wait=True)["counters"]
     dt = time.perf_counter() - t
     job.release()
@@ -293,9 +328,10 @@ def full_histories_section(n_photons):
     """The halo (128^3, its configuration: local and non-local core-skipping,
     8 cameras) and the NFW octree (~2e6 leaves, 4 cameras) followed to the end
     of every history, on a subsample: the job's first n_photons photon ids (the
-    same photons as in the 1e7-photon jobs).  Their histories are heavy-tailed
-    (~8e5 scatterings per halo photon on average, some over 5e6), so the last
-    photons run nearly alone and the run's time includes that tail."""
+    same photons as in the 1e7-photon jobs; 1e6 by default).  Their histories
+    are heavy-tailed (~7.6e5 scatterings per halo photon on average, 4.2e4 per
+    octree photon, a few far more), so the last photons run nearly alone for
+    tens of seconds and the run's time includes that tail."""
     from paper_1409_4480_amd import colt, inputs
 
     out = {}
@@ -304,7 +340,7 @@ def full_histories_section(n_photons):
                         lambda: inputs.nfw_octree(n_photons=n_photons))):
         wl = make()
         grid = colt.Grid(wl["grid"])
-        c, dt, n = timed_job(grid, wl, colt.FP32_BULK)
+        c, dt, n = timed_job(grid, wl, colt.FP32_BULK, progress=name)
         grid.release()
         out[name] = workload_figures(c, dt, n, {"sample": f"photon ids 0..{n_photons - 1} of "
                                                           f"the 1e7-photon job, full histories"})
@@ -323,8 +359,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
-    ap.add_argument("--streams", type=int, default=4,
+    ap.add_argument("--streams", type=int, default=8,
                     help="streams the steps are queued on in turn (1: one step at a time)")
+    ap.add_argument("--pipe-blocks-per-cu", type=int, default=2,
+                    help="resident workgroups per CU of each pipelined step's launch (2: a "
+                         "step takes half of the device, so two or more run side by side; "
+                         "0: the kernel's limit)")
     ap.add_argument("--tail-live", type=int, default=0,
                     help="pipelined steps: once a step's photons are all handed out, waves "
                          "with fewer live photons hand them to the next of its launches "
@@ -340,7 +380,7 @@ def main():
                     help="jobs in the serving stream (0 skips the serving section)")
     ap.add_argument("--serve-scaled", action="store_true",
                     help="serve the smaller stream (32^3-64^3, tau0 <= 1e5, <= 5e4 photons)")
-    ap.add_argument("--full-photons", type=int, default=4096,
+    ap.add_argument("--full-photons", type=int, default=1_000_000,
                     help="photons of the halo and octree followed to the end of their "
                          "histories (0 skips)")
     ap.add_argument("--only-workload", default=None,
@@ -397,7 +437,7 @@ def main():
             st = sts[i % len(sts)]
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(st)
-            colt.transport([j], block=args.block, blocks_per_cu=args.blocks_per_cu,
+            colt.transport([j], block=args.block, blocks_per_cu=args.pipe_blocks_per_cu,
                            stream=ctypes.c_void_p(st.cuda_stream), tail_live=args.tail_live,
                            launches=args.launches)
             e1.record(st)
@@ -463,7 +503,8 @@ def main():
                    "core_skip": "global x_crit(a tau0=4702)=3.35", "photons_per_step": args.photons,
                    "spectrum_bins": 500, "precision": "FP32-bulk"},
         "photons_per_s": photons / el,
-        "streams": args.streams, "tail_live": args.tail_live, "launches_per_step": args.launches,
+        "streams": args.streams, "pipelined_blocks_per_cu": args.pipe_blocks_per_cu,
+        "tail_live": args.tail_live, "launches_per_step": args.launches,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "of": "one step alone, launch to tallies on the host"},
         "per_step": {"scatterings": scat / args.steps,
