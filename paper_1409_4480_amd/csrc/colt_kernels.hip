@@ -557,6 +557,9 @@ __device__ __forceinline__ void peel_event(const JobView &J, const double *cams,
 {
     using F = Fn<R>;
     const R wn = R(1) + F::div(ps.rW, R(3));
+    // every camera's estimate crosses at least the event's own cell
+    lc.add(C_PEELS, (uint32_t)J.n_cams);
+    lc.add(C_PEEL_CROSSINGS, (uint32_t)J.n_cams);
     for (int i = 0; i < J.n_cams; ++i) {
         const double *cam = cams + 12 * i;
         const double d[3] = {cam[0], cam[1], cam[2]};
@@ -567,8 +570,6 @@ __device__ __forceinline__ void peel_event(const JobView &J, const double *cams,
         const R xc = ps.base + (dr[0] * ps.ua[0] + dr[1] * ps.ua[1] + dr[2] * ps.ua[2]) +
                      ps.grec * (muc - R(1));
         const R xl = F::div(xc + (dr[0] * cr.ux + dr[1] * cr.uy + dr[2] * cr.uz), cr.s);
-        lc.add(C_PEELS);
-        lc.add(C_PEEL_CROSSINGS);
         double l;
         int axis;
         bool by_sphere;

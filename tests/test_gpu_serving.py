@@ -1,5 +1,5 @@
 """Serving: continuous batching of uneven jobs gives each job the result it
-gets alone (FP64 photon records bit for bit), admission by memory budget
+gets alone (FP64 and FP32-bulk photon records bit for bit), admission by memory budget
 queues jobs without changing results, and latencies are reported."""
 import numpy as np
 import pytest
@@ -18,14 +18,18 @@ def small_stream(n=6, seed=3):
     return jobs
 
 
-def test_each_job_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("prec", [colt.FP64, colt.FP32_BULK])
+def test_each_job_same_alone_and_in_the_mix(prec):
+    """Every job's records are the same bit for bit when served in a mix of
+    epochs (the multi-job kernel, slices of uneven jobs) as when run alone (in
+    FP32-bulk, the one-job kernel compiled for its grid kind)."""
     jobs = small_stream()
-    say(f"[gpu] serving mix of {len(jobs)} jobs")
-    srv = serving.Server(epoch_photons=2048, min_quota=256, precision=colt.FP64, record=True)
+    say(f"[gpu] serving mix of {len(jobs)} jobs, precision {prec}")
+    srv = serving.Server(epoch_photons=2048, min_quota=256, precision=prec, record=True)
     mixed = srv.run(jobs, realtime=False)
     assert srv.max_active == len(jobs) and srv.epochs > 1
     for wl, m in zip(jobs, mixed):
-        alone = colt.run(wl, precision=colt.FP64, record=True)
+        alone = colt.run(wl, precision=prec, record=True)
         for k in ("x", "nscat", "status", "pos"):
             assert np.array_equal(alone["records"][k], m["records"][k]), (wl["name"], k)
         assert np.array_equal(alone["spectrum"], m["spectrum"])
