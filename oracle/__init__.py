@@ -55,7 +55,7 @@ class _Out(ctypes.Structure):
     _fields_ = [("spectrum", _dp), ("cam_spec", _dp), ("cam_img", _dp),
                 ("counters", ctypes.c_uint64 * N_COUNTERS), ("rec_x", _dp),
                 ("rec_nscat", _ip), ("rec_status", _ip), ("rec_pos", _dp),
-                ("rec_peel", _dp), ("rec_len", _dp)]
+                ("rec_peel", _dp), ("rec_len", _dp), ("rec_ndust", _ip)]
 
 
 _libs = {}
@@ -334,13 +334,15 @@ def run(grid, source, params, id_begin=0, id_end=None, records=False, threads=No
     if records:
         rec = {"x": np.zeros(n_run), "nscat": np.zeros(n_run, np.int32),
                "status": np.zeros(n_run, np.int32), "pos": np.zeros((n_run, 3)),
-               "peel": np.zeros((n_run, max(n_cams, 1))), "len": np.zeros(n_run)}
+               "peel": np.zeros((n_run, max(n_cams, 1))), "len": np.zeros(n_run),
+               "ndust": np.zeros(n_run, np.int32)}
         o.rec_x = _ptr(rec["x"])
         o.rec_nscat = _ptr(rec["nscat"], _ip)
         o.rec_status = _ptr(rec["status"], _ip)
         o.rec_pos = _ptr(rec["pos"])
         o.rec_peel = _ptr(rec["peel"]) if n_cams else None
         o.rec_len = _ptr(rec["len"])
+        o.rec_ndust = _ptr(rec["ndust"], _ip)
     rc = lib(variant).orc_run(ctypes.byref(g), ctypes.byref(s), ctypes.byref(p),
                               ctypes.byref(o), int(threads))
     if rc != 0:

@@ -94,6 +94,7 @@ typedef struct {
     double *rec_pos;           /* 3 per photon, final position (cm)                   */
     double *rec_peel;          /* n_cams per photon, summed W exp(-tau)               */
     double *rec_len;           /* path length travelled from emission to the end (cm) */
+    int32_t *rec_ndust;        /* dust scatterings                                    */
 } orc_out;
 
 /* Runs photons [id_begin, id_end) with n_threads worker threads; returns 0 or <0. */

@@ -5,11 +5,11 @@
  * opacity competing with H I at each interaction point.
  * TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
- * Pins: every step is checked against a closed form or a limit in the tests,
- * except dust scattering at intermediate albedo inside H I gas (parity
- * unpinned there: only the albedo-0 attenuation identity and the albedo-1
- * no-loss limit are pinned), and the wind and turbulent workloads, whose
- * spectra the paper does not print (parity unpinned).
+ * Pins: every step is checked against a closed form, a limit or an exact
+ * invariant in the tests (dust at any albedo through the coupling of its
+ * histories to the albedo-1 ones), except the wind and turbulent workloads,
+ * whose spectra the paper does not print (parity unpinned; their frame
+ * transformations are pinned by Galilean invariance).
  *
  * Draw order of one photon's stream (the written contract both
  * implementations follow):
@@ -264,6 +264,7 @@ static void run_photon(orc_job *J, uint64_t id, orc_tally *T)
     int status;
     double x_lab = 0.0;
     double path = 0.0;                          /* distance travelled (record only) */
+    int32_t ndust = 0;                          /* dust scatterings (record only) */
     if (!orc_locate(g, r, k, &c)) {             /* born outside the domain: escapes */
         status = 1;
         T->counters[ORC_ESCAPED] += 1;
@@ -321,6 +322,7 @@ static void run_photon(orc_job *J, uint64_t id, orc_tally *T)
             isotropic_dir(&st, k);              /* grey isotropic dust scattering */
             x_lab = lab_x(C, ci, x, k);         /* comoving frequency unchanged */
             T->counters[ORC_SCAT_DUST] += 1;
+            ++ndust;
             if (p->n_cams > 0) {
                 for (int i = 0; i < p->n_cams; ++i) { xcam[i] = x; W[i] = 1.0; }
                 peel_off(J, &c, r, xcam, W, T, rec_peel);
@@ -364,6 +366,7 @@ done:
     if (o->rec_status) o->rec_status[slot] = status;
     if (o->rec_pos) for (int d = 0; d < 3; ++d) o->rec_pos[3 * slot + d] = r[d];
     if (o->rec_len) o->rec_len[slot] = path;
+    if (o->rec_ndust) o->rec_ndust[slot] = ndust;
 }
 
 typedef struct { orc_job *J; int t; } orc_worker_arg;

@@ -273,6 +273,39 @@ def test_dust_with_hi_is_attenuation_along_the_walk(threads, tau_d):
     assert c["escaped"] == n and c["absorbed"] == 0 and c["scat_dust"] > 0
 
 
+@pytest.mark.parametrize("albedo", [0.32, 0.75])
+def test_dust_at_any_albedo_is_the_albedo_one_walk_cut_short(threads, albedo):
+    """Dust at intermediate albedo inside H I gas.  A dust event draws one
+    uniform R' and the photon is absorbed when R' >= albedo, so with the same
+    photon streams the run at albedo A follows the albedo-1 history of every
+    photon up to its first dust event with R' >= A.  Hence: the photons that
+    escape at A end exactly as they do at albedo 1 (same frequency, position,
+    scatterings and dust events), each absorbed one had more dust events at
+    albedo 1 than before its absorption, and the escaped count is
+    sum_i A^k_i over the albedo-1 histories (k_i dust events each) within its
+    binomial error."""
+    n = 6000
+    w = inputs.static_sphere(n=8, tau0=1e3, n_photons=n, seed=63, isotropic=False,
+                             k_dust=0.5 / PC, albedo=1.0)
+    one = oracle.run(w["grid"], w["source"], w["params"], records=True,
+                     threads=threads)["records"]
+    w["grid"]["albedo"] = albedo
+    part = oracle.run(w["grid"], w["source"], w["params"], records=True,
+                      threads=threads)["records"]
+    assert (one["status"] == 1).all()
+    esc = part["status"] == 1
+    absorbed = part["status"] == 2
+    assert (esc | absorbed).all()
+    for key in ("x", "nscat", "pos", "ndust", "len"):
+        assert np.array_equal(one[key][esc], part[key][esc]), key
+    assert (part["ndust"][absorbed] < one["ndust"][absorbed]).all()
+    k = one["ndust"].astype(np.float64)
+    assert k.mean() > 1.0                       # several dust events per photon
+    p = albedo ** k
+    expected, sd = p.sum(), math.sqrt((p * (1 - p)).sum())
+    assert abs(esc.sum() - expected) < 4.0 * sd, (esc.sum(), expected, sd)
+
+
 def test_dusty_sphere_conservation(threads):
     w = inputs.dusty_sphere(n=8, tau0=1e5, n_photons=1000, seed=41)
     out = oracle.run(w["grid"], w["source"], w["params"], records=True, threads=threads)
