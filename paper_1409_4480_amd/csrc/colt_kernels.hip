@@ -1162,7 +1162,9 @@ constexpr uint32_t kHostPoll = 32;
 // still in flight (the rest resume in the next pass, so one long flight does
 // not hold the whole wave); the wave then serves all parallel-velocity draws
 // cooperatively and completes the scatterings.  At the end of a pass the wave
-// checks for a stop request; a stopped wave suspends its photons and leaves.
+// checks for a stop request (or, under the tail rule, whether it holds fewer
+// than L.tail_live photons once both queues are empty); a stopped wave
+// suspends its photons and leaves.
 // A photon's history does not depend on where passes cut its flights or on
 // where the launch was stopped.
 // SINGLE launches carry one job.  The FP32 kernels take it by value as J1:
