@@ -141,6 +141,29 @@ def test_halo_full_histories():
         assert abs(gr["peel"][:, c].mean() - rr["peel"][:, c].mean()) < 4 * se, c
 
 
+def test_octree_full_histories():
+    """The ~2e6-leaf NFW octree job as configured (local and non-local
+    core-skipping, f_NL = 1/2, 64 sources, 4 cameras): its first 1024 photons
+    followed to escape, ~4e4 scatterings each on average and over 1e6 for a
+    few.  Histories equal the oracle's up to the share that rounding alone
+    turns (measured on the oracle), and the two samples agree in escape
+    frequency, scattering counts and camera fluxes."""
+    n = 1024
+    wl = inputs.nfw_octree(n_photons=n)
+    say(f"[gpu] NFW octree {wl['leaves']} leaves, {n} photons, full histories")
+    g = colt.run(wl, precision=colt.FP64, record=True)
+    r = oracle.run(oracle_grid(wl["grid"]), wl["source"], wl["params"], records=True)
+    gr, rr = g["records"], r["records"]
+    say(f"    scatterings per photon: GPU {gr['nscat'].mean():.0f}, oracle {rr['nscat'].mean():.0f}")
+    assert (gr["status"] == 1).all() and (rr["status"] == 1).all()
+    compare_records(g, r, 4000 * PC, peel=True, flip=measured_flip(wl))
+    for key in ("x", "nscat"):
+        assert sst.ks_2samp(gr[key], rr[key]).pvalue > 0.01, key
+    for c in range(gr["peel"].shape[1]):
+        se = math.sqrt((gr["peel"][:, c].var() + rr["peel"][:, c].var()) / n) + 1e-300
+        assert abs(gr["peel"][:, c].mean() - rr["peel"][:, c].mean()) < 4 * se, c
+
+
 def test_octree_full_size_capped_histories():
     """~2e6-leaf NFW octree (64^3 base + 4 levels), 64 sources, 4 cameras of
     512^2 pixels; 64 photons followed to 5000 events each."""
