@@ -529,6 +529,13 @@ def main():
                                        "run (pipelined steps overlap, so their spans include "
                                        "time shared with the next step)",
                      "pipelined_span_ms": float(np.mean(span)),
+                     "timed_region": {
+                         "ops": float(sum(algorithmic_ops(c) for c in cnt)),
+                         "elapsed_ms": el * 1e3,
+                         "achieved": sum(algorithmic_ops(c) for c in cnt) / el / 1e12,
+                         "frac": sum(algorithmic_ops(c) for c in cnt) / el / VALU_PEAK,
+                         "note": "all the timed steps' algorithmic lane-ops over the timed "
+                                 "region's wall time (the steps overlap on the device)"},
                      "ops_per_launch": ops,
                      "ops_model": "335 + 83 n lane-ops per H I scattering (n u_par candidates), "
                                   "34 per cell crossing",
