@@ -107,5 +107,13 @@ def test_invalid_samplers_and_launches_are_rejected():
     arr = (ctypes.c_void_p * 1)(None)
     assert L.colt_transport(arr, 0, ctypes.byref(lc), None) == -1
     assert L.colt_transport(arr, 1, None, None) == -1     # null job handle
+    for bad in (colt.Launch(0, 0, 0, 0, 0, 0, 65, 0),     # tail_live beyond a wave
+                colt.Launch(0, 0, 0, 0, 0, 0, -1, 0),
+                colt.Launch(0, 0, 0, 0, 0, 0, 0, -2),     # negative launch count
+                colt.Launch(0, 0, 0, 0, 0, 64, 0, 0)):    # stop token beyond 63
+        assert L.colt_transport(arr, 0, ctypes.byref(bad), None) == -1
+        assert L.colt_transport_static(arr, 0, ctypes.byref(bad), None) == -1
+    ok = colt.Launch(0, 0, 0, 0, 0, 0, 16, 4)             # an empty job list does nothing
+    assert L.colt_transport(arr, 0, ctypes.byref(ok), None) == 0
     assert L.colt_release_grid(None) == 0
     assert L.colt_last_kernel_ms() < 0
