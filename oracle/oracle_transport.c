@@ -7,9 +7,10 @@
  *
  * Pins: every step is checked against a closed form, a limit or an exact
  * invariant in the tests (dust at any albedo through the coupling of its
- * histories to the albedo-1 ones), except the wind and turbulent workloads,
- * whose spectra the paper does not print (parity unpinned; their frame
- * transformations are pinned by Galilean invariance).
+ * histories to the albedo-1 ones; bulk flows through Galilean invariance, the
+ * unscattered Doppler shift and the expanding sphere's mirror symmetry).  The
+ * wind and turbulent workloads have no spectra in the paper to compare with,
+ * but every function they exercise is among those pinned.
  *
  * Draw order of one photon's stream (the written contract both
  * implementations follow):
