@@ -51,7 +51,7 @@ def test_512_jobs_in_one_launch_equal_each_job_alone():
                for f, w in zip(fused, wls))
 
 
-@pytest.mark.parametrize("case", ["dusty", "halo"])
+@pytest.mark.parametrize("case", ["dusty", "halo", "octree"])
 def test_fp32_job_alone_equals_the_job_in_a_fused_launch(case):
     """FP32-bulk: a one-job launch (its job passed to the kernel by value, the
     kernel compiled for the grid kind) and a launch that fuses the job with
@@ -62,8 +62,15 @@ def test_fp32_job_alone_equals_the_job_in_a_fused_launch(case):
     if case == "dusty":
         wl = inputs.dusty_sphere(n=16, tau0=1e5, n_photons=20000, seed=3)
         cap = 0
-    else:
+    elif case == "halo":
         wl = inputs.halo(n=32, n_photons=8000, seed=4)
+        cap = 3000
+        wl["params"]["max_events"] = cap
+    else:
+        # FP32 octree records share their line with the leaf's links: the
+        # one-job kernel has those strides compiled in, the fused one reads them
+        wl = inputs.nfw_octree(base_level=3, max_extra=3, leaves_target=(4000, 9000),
+                               turb_n=16, n_photons=4000, npix=32, n_bins=100, tau0_max=1e5)
         cap = 3000
         wl["params"]["max_events"] = cap
     n = wl["params"]["n_photons"]
@@ -87,7 +94,7 @@ def test_fp32_job_alone_equals_the_job_in_a_fused_launch(case):
     for k in ("x", "nscat", "status", "pos"):
         assert np.array_equal(a[k], f[k]), k
     assert np.array_equal(alone["spectrum"], fused["spectrum"])
-    if case == "halo":
+    if case != "dusty":
         assert np.allclose(a["peel"], f["peel"], rtol=1e-12, atol=1e-300)
         for key in ("cam_spec", "cam_img"):
             assert np.allclose(alone[key], fused[key], rtol=1e-12,
