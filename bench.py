@@ -432,6 +432,9 @@ def main():
         jobs = [colt.Job(grid, wl["source"], dict(wl["params"], seed=seed0 + i),
                          precision=precision) for i in range(n_steps)]
         sts = [torch.cuda.Stream() for _ in range(max(1, streams))]
+        for st in sts:          # every stream has its hardware queue before the clock starts
+            with torch.cuda.stream(st):
+                torch.ones(1, device="cuda").add_(1.0)
         torch.cuda.synchronize()
         marks = []
         t_start = time.perf_counter()

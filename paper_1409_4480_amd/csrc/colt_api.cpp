@@ -220,6 +220,10 @@ void dev_free(const colt_allocator &a, bool custom, void *p)
 // Reusable launch tables: device memory from the jobs' allocator plus pinned
 // host staging, recycled once the event recorded after their launch has
 // completed.  Tables are kept per allocator and are never returned to it.
+// Small tables come in batches cut from one device and one pinned host
+// allocation, so a burst of launches in flight (steps queued on several
+// streams) does not allocate per launch.  A table handed out is busy until its
+// event is recorded, so concurrent callers never share one.
 struct LaunchBuf {
     void *dev = nullptr;
     void *host = nullptr;
@@ -227,9 +231,12 @@ struct LaunchBuf {
     hipEvent_t done = nullptr;
     colt_allocator alloc{};
     bool custom = false;
+    bool busy = false;
 };
 std::mutex g_pool_mu;
 std::vector<LaunchBuf *> g_pool;
+constexpr size_t kLaunchSlot = 16384;     // bytes of a small table
+constexpr int kLaunchBatch = 16;          // small tables allocated together
 
 bool same_allocator(const LaunchBuf *b, const colt_allocator &a, bool custom)
 {
@@ -242,30 +249,61 @@ LaunchBuf *acquire_launch_buf(size_t bytes, const colt_allocator &a, bool custom
 {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (LaunchBuf *b : g_pool) {
-        if (b->size >= bytes && same_allocator(b, a, custom) &&
-            hipEventQuery(b->done) == hipSuccess)
+        if (!b->busy && b->size >= bytes && same_allocator(b, a, custom) &&
+            hipEventQuery(b->done) == hipSuccess) {
+            b->busy = true;
             return b;
+        }
     }
-    LaunchBuf *b = new LaunchBuf();
-    b->size = std::max<size_t>((bytes + 4095) & ~size_t(4095), 4096);
-    b->alloc = a;
-    b->custom = custom;
-    b->dev = dev_alloc(a, custom, b->size);
-    if (!b->dev) { delete b; return nullptr; }
-    if (hipHostMalloc(&b->host, b->size, hipHostMallocDefault) != hipSuccess) {
-        dev_free(a, custom, b->dev);
-        delete b;
+    const bool small = bytes <= kLaunchSlot;
+    const size_t slot = small ? kLaunchSlot : std::max<size_t>((bytes + 4095) & ~size_t(4095), 4096);
+    const int n = small ? kLaunchBatch : 1;
+    void *dev = dev_alloc(a, custom, slot * n);
+    if (!dev) return nullptr;
+    void *host = nullptr;
+    if (hipHostMalloc(&host, slot * n, hipHostMallocDefault) != hipSuccess) {
+        dev_free(a, custom, dev);
         return nullptr;
     }
-    if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
-        dev_free(a, custom, b->dev);
-        (void)hipHostFree(b->host);
-        delete b;
+    LaunchBuf *first = nullptr;
+    for (int k = 0; k < n; ++k) {
+        LaunchBuf *b = new LaunchBuf();
+        b->size = slot;
+        b->dev = (char *)dev + (size_t)k * slot;
+        b->host = (char *)host + (size_t)k * slot;
+        b->alloc = a;
+        b->custom = custom;
+        if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+            delete b;
+            break;
+        }
+        g_pool.push_back(b);
+        if (!first) first = b;
+    }
+    if (!first) {               // nothing refers to the memory: give it back
+        dev_free(a, custom, dev);
+        (void)hipHostFree(host);
         return nullptr;
     }
-    g_pool.push_back(b);
-    return b;
+    first->busy = true;
+    return first;
 }
+
+// Holds a table for one launch: on release its event has been recorded on the
+// launch's stream (here, if an error cut the launch short), so the table is
+// reused only after everything queued with it has run.
+struct LaunchHold {
+    LaunchBuf *b = nullptr;
+    hipStream_t s = nullptr;
+    bool recorded = false;
+    ~LaunchHold()
+    {
+        if (!b) return;
+        if (!recorded) (void)hipEventRecord(b->done, s);
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        b->busy = false;
+    }
+};
 
 // Host stop words (colt_stop_set): pinned, device-mapped, coherent memory the
 // transport kernel polls.
@@ -1191,6 +1229,7 @@ colt_status transport_impl(const colt_job *jobs, int32_t n_jobs, const colt_laun
                                             launch ? launch->blocks_per_cu : 0, &grid);
         if (st != COLT_OK) return st;
         const TableLayout t = table_layout(nj);
+        LaunchHold hold;
         LaunchBuf *b = nullptr;
         char *table = nullptr;
         if (fixed) {
@@ -1203,6 +1242,8 @@ colt_status transport_impl(const colt_job *jobs, int32_t n_jobs, const colt_laun
         } else {
             b = acquire_launch_buf(t.bytes, members[0]->mem.alloc, members[0]->mem.custom);
             if (!b) return fail(COLT_ERR_NOMEM, "launch table allocation failed");
+            hold.b = b;
+            hold.s = s;
             std::memset(b->host, 0, t.bytes);
             std::memcpy((char *)b->host + t.jobs, views.data(), sizeof(JobView) * nj);
             HIP_TRY(hipMemcpyAsync(b->dev, b->host, t.bytes, hipMemcpyHostToDevice, s));
@@ -1221,7 +1262,10 @@ colt_status transport_impl(const colt_job *jobs, int32_t n_jobs, const colt_laun
                                     (timed && rep == 0) ? g_t0 : nullptr,
                                     (timed && rep == reps - 1) ? g_t1 : nullptr));
         if (timed) g_timed = true;
-        if (b) HIP_TRY(hipEventRecord(b->done, s));
+        if (b) {
+            HIP_TRY(hipEventRecord(b->done, s));
+            hold.recorded = true;
+        }
         for (colt_job j : members) {
             if (!j->uncertain && !may_stop) {
                 const uint64_t left = j->params.n_photons - j->h_cursor;
