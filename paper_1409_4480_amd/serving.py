@@ -41,6 +41,9 @@ def footprint(wl, record=False, precision=colt.FP32_BULK):
     return n + (64 << 10)
 
 
+_EPOCH_TOKEN0 = 40                     # stop tokens of bounded epochs: 40 .. 40 + depth - 1
+
+
 class _Active:
     __slots__ = ("wl", "grid", "job", "arrival", "admitted", "bytes", "index")
 
@@ -51,10 +54,17 @@ class Server:
     budget_bytes    device memory the server may hold (None: 90 % of free HBM)
     epoch_photons   photons per epoch, split evenly over the active jobs
     min_quota       smallest per-job slice of an epoch
+    depth           epochs in flight at once, each on a stream of its own
+    epoch_ms        None, or a time after which a running epoch is asked to stop:
+                    its photons in flight are suspended and resume, bit for bit,
+                    in a later epoch, so the jobs whose photons are done leave
+                    without waiting for the longest histories of the others
+                    (a job is then in one epoch at a time)
     """
 
     def __init__(self, budget_bytes=None, epoch_photons=1 << 20, min_quota=8192,
-                 precision=colt.FP32_BULK, record=False, block=0, blocks_per_cu=0, depth=2):
+                 precision=colt.FP32_BULK, record=False, block=0, blocks_per_cu=0, depth=2,
+                 epoch_ms=None):
         import torch
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
@@ -67,6 +77,9 @@ class Server:
         self.block = block
         self.blocks_per_cu = blocks_per_cu
         self.depth = max(1, int(depth))
+        if epoch_ms is not None and self.depth > 64 - _EPOCH_TOKEN0:
+            raise ValueError(f"bounded epochs take one stop token each: depth <= {64 - _EPOCH_TOKEN0}")
+        self.epoch_ms = epoch_ms
         self._torch = torch
 
     def run(self, workloads, realtime=True):
@@ -84,9 +97,11 @@ class Server:
         streams = [torch.cuda.Stream() for _ in range(self.depth)]
         results = [None] * len(workloads)
         active = []
-        inflight = deque()             # (event, ids of the jobs in that epoch)
+        inflight = deque()             # [event, ids of the jobs, stream slot, start, stop asked]
+        bounded = self.epoch_ms is not None
         used = 0
         epochs = 0
+        self.stopped = 0
         self.max_active = 0
         self.max_used = 0
         t0 = time.perf_counter()
@@ -109,22 +124,41 @@ class Server:
                 self.max_used = max(self.max_used, used)
                 active.append(a)
             self.max_active = max(self.max_active, len(active))
-            ready = [a for a in active if a.job.status()[0] < a.job.status()[1]]
+            busy = set()
+            for x in inflight:
+                busy |= x[1]
+            # a job whose launches may have stopped is asked only when idle (its
+            # status waits for its launches)
+            ready = [a for a in active if not (bounded and id(a) in busy)
+                     and a.job.status()[0] < a.job.status()[1]]
             if ready and len(inflight) < self.depth:
                 quota = max(self.min_quota, self.epoch_photons // len(ready))
-                st = streams[epochs % self.depth]
+                slot = next(k for k in range(self.depth) if k not in {x[2] for x in inflight})
+                st = streams[slot]
                 st.wait_stream(torch.cuda.current_stream())     # the jobs' uploads
+                token = 0
+                if bounded:
+                    token = _EPOCH_TOKEN0 + slot
+                    colt.stop_set(token, False)
                 colt.transport([a.job for a in ready], photons_per_job=quota, block=self.block,
                                blocks_per_cu=self.blocks_per_cu,
-                               stream=ctypes.c_void_p(st.cuda_stream))
+                               stream=ctypes.c_void_p(st.cuda_stream), stop_token=token)
                 ev = torch.cuda.Event()
                 ev.record(st)
-                inflight.append((ev, {id(a) for a in ready}))
+                inflight.append([ev, {id(a) for a in ready}, slot, time.perf_counter(), False])
                 epochs += 1
                 continue
             if inflight:
-                # wait for an epoch to end, or for the next arrival to admit it
-                while not any(e.query() for e, _ in inflight):
+                # wait for an epoch to end, or for the next arrival to admit it;
+                # a bounded epoch past its time is asked to stop
+                while not any(x[0].query() for x in inflight):
+                    if bounded:
+                        tnow = time.perf_counter()
+                        for x in inflight:
+                            if not x[4] and (tnow - x[3]) * 1e3 > self.epoch_ms:
+                                colt.stop_set(_EPOCH_TOKEN0 + x[2], True)
+                                x[4] = True
+                                self.stopped += 1
                     if realtime and pending and \
                             time.perf_counter() - t0 >= workloads[pending[0]].get("arrival", 0.0):
                         break
@@ -135,12 +169,15 @@ class Server:
                 time.sleep(max(0.0, min(nxt - (time.perf_counter() - t0), 0.05)))
                 continue
             busy = set()
-            for _, ids in inflight:
-                busy |= ids
+            for x in inflight:
+                busy |= x[1]
             still = []
             for a in active:
+                if id(a) in busy:
+                    still.append(a)
+                    continue
                 launched, total = a.job.status()
-                if launched < total or id(a) in busy:
+                if launched < total:
                     still.append(a)
                     continue
                 out = a.job.tally(wait=True)

@@ -37,6 +37,29 @@ def test_each_job_same_alone_and_in_the_mix(prec):
             assert alone["counters"][k] == m["counters"][k]
 
 
+@pytest.mark.parametrize("prec", [colt.FP64, colt.FP32_BULK])
+def test_bounded_epochs_stop_and_resume_bit_for_bit(prec):
+    """With a time bound of zero every epoch is asked to stop as soon as the
+    host sees it running: photons in flight are suspended and resumed in later
+    epochs, and every job still gets the records it gets alone."""
+    jobs = small_stream(n=5, seed=9)
+    say(f"[gpu] serving with bounded epochs, {len(jobs)} jobs, precision {prec}")
+    free = serving.Server(epoch_photons=2048, min_quota=256, precision=prec, record=True)
+    free.run(jobs, realtime=False)
+    srv = serving.Server(epoch_photons=2048, min_quota=256, precision=prec, record=True,
+                         epoch_ms=0.0)
+    mixed = srv.run(jobs, realtime=False)
+    say(f"    epochs {srv.epochs} ({srv.stopped} asked to stop), unbounded {free.epochs}")
+    assert srv.stopped > 0 and srv.epochs > free.epochs
+    for wl, m in zip(jobs, mixed):
+        alone = colt.run(wl, precision=prec, record=True)
+        for k in ("x", "nscat", "status", "pos"):
+            assert np.array_equal(alone["records"][k], m["records"][k]), (wl["name"], k)
+        assert np.array_equal(alone["spectrum"], m["spectrum"])
+        for k in ("emitted", "escaped", "scat_hi", "upar_tries", "crossings"):
+            assert alone["counters"][k] == m["counters"][k]
+
+
 def test_admission_footprint_bounds_the_device_bytes():
     """The server admits by an estimate made before anything is allocated; it
     must not undercount what the library then holds for the grid and the job
