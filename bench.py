@@ -252,7 +252,7 @@ def timed_job(grid, wl, precision, cap=0, progress=None):
                 colt.stop_set(PROGRESS_TOKEN, False)
                 colt.transport([job], stop_token=PROGRESS_TOKEN)
                 n += 1
-                job.tally(wait=True)
+                torch.cuda.synchronize()
                 now = time.perf_counter()
                 if now - last > 15.0:
                     nxt, n_susp, _ = job.pending()
@@ -326,7 +326,7 @@ def workloads_section(n_photons=262144, cap=2000, only=None):
     return out
 
 
-def full_histories_section(n_photons):
+def full_histories_section(n_photons, only=None):
     """The halo (128^3, its configuration: local and non-local core-skipping,
     8 cameras) and the NFW octree (~2e6 leaves, 4 cameras) followed to the end
     of every history, on a subsample: the job's first n_photons photon ids (the
@@ -337,15 +337,20 @@ def full_histories_section(n_photons):
     from paper_1409_4480_amd import colt, inputs
 
     out = {}
-    for name, make in (("halo_128cube_8cams_full", lambda: inputs.halo(n_photons=n_photons)),
-                       ("nfw_octree_2e6_leaves_4cams_full",
-                        lambda: inputs.nfw_octree(n_photons=n_photons))):
+    cases = (("halo_128cube_8cams_full", lambda: inputs.halo(n_photons=n_photons)),
+             ("nfw_octree_2e6_leaves_4cams_full", lambda: inputs.nfw_octree(n_photons=n_photons)))
+    if only:
+        cases = [c for c in cases if c[0] == only]
+        if not cases:
+            raise SystemExit(f"no full-history workload named {only!r}")
+    for name, make in cases:
         wl = make()
         grid = colt.Grid(wl["grid"])
         c, dt, n = timed_job(grid, wl, colt.FP32_BULK, progress=name)
         grid.release()
-        out[name] = workload_figures(c, dt, n, {"sample": f"photon ids 0..{n_photons - 1} of "
-                                                          f"the 1e7-photon job, full histories"})
+        sample = ("the whole 1e7-photon job" if n_photons == 10_000_000 else
+                  f"photon ids 0..{n_photons - 1} of the 1e7-photon job")
+        out[name] = workload_figures(c, dt, n, {"sample": sample + ", full histories"})
         print(f"# {name}: {dt:.1f} s, {out[name]['scatterings_per_photon']:.3g} scatterings "
               f"per photon", file=sys.stderr, flush=True)
     return out
@@ -388,6 +393,9 @@ def main():
     ap.add_argument("--only-workload", default=None,
                     help="only run this entry of the workloads section (e.g. halo_128cube_8cams) "
                          "and print its figures")
+    ap.add_argument("--only-full", default=None,
+                    help="only follow this full-history workload (e.g. "
+                         "nfw_octree_2e6_leaves_4cams_full) for --full-photons photons")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -414,6 +422,9 @@ def main():
         return
     if args.only_workload:
         print(json.dumps(workloads_section(only=args.only_workload)))
+        return
+    if args.only_full:
+        print(json.dumps(full_histories_section(args.full_photons, only=args.only_full)))
         return
     stream = torch.cuda.current_stream()
     wl = workload(args.photons, 1409448002)
