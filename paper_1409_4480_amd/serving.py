@@ -82,10 +82,11 @@ class Server:
         self.epoch_ms = epoch_ms
         self._torch = torch
 
-    def run(self, workloads, realtime=True):
+    def run(self, workloads, realtime=True, on_done=None):
         """Serves the jobs; returns one result dict per job, in input order.
 
-        With realtime=False every job is taken as arrived at time 0.
+        With realtime=False every job is taken as arrived at time 0.  on_done,
+        if given, is called as on_done(index, result) as each job finishes.
         """
         order = sorted(range(len(workloads)),
                        key=lambda i: workloads[i].get("arrival", 0.0) if realtime else 0.0)
@@ -186,6 +187,8 @@ class Server:
                 out["queue_s"] = a.admitted - a.arrival
                 out["finished_s"] = done
                 results[a.index] = out
+                if on_done is not None:
+                    on_done(a.index, out)
                 a.job.release()
                 a.grid.release()
                 used -= a.bytes
