@@ -45,7 +45,18 @@ _EPOCH_TOKEN0 = 40                     # stop tokens of bounded epochs: 40 .. 40
 
 
 class _Active:
-    __slots__ = ("wl", "grid", "job", "arrival", "admitted", "bytes", "index")
+    __slots__ = ("wl", "grid", "job", "arrival", "admitted", "bytes", "index", "tier")
+
+
+def line_depth(wl):
+    """A proxy, for ranking jobs only, of how long a job's photon histories
+    run: the largest n_HI / sqrt(T) of its cells (the line-centre opacity
+    scales so) times half the domain's widest extent."""
+    g = wl["grid"]
+    n = np.asarray(g["n_HI"], float)
+    t = np.asarray(g["T"], float)
+    width = float(np.max(np.asarray(g["box_max"], float) - np.asarray(g["box_min"], float)))
+    return float(np.max(n / np.sqrt(t))) * 0.5 * width
 
 
 class Server:
@@ -60,11 +71,18 @@ class Server:
                     in a later epoch, so the jobs whose photons are done leave
                     without waiting for the longest histories of the others
                     (a job is then in one epoch at a time)
+    split           keep jobs with long photon histories out of the epochs of
+                    jobs with short ones: each job falls in one of `depth`
+                    tiers by the rank of its line_depth among the jobs admitted
+                    so far, and stream slot k runs epochs of tier k (or, when
+                    it has nothing ready, of the nearest lighter tier), so a
+                    short job's epoch does not last as long as the longest
+                    histories of the mix
     """
 
     def __init__(self, budget_bytes=None, epoch_photons=1 << 20, min_quota=8192,
                  precision=colt.FP32_BULK, record=False, block=0, blocks_per_cu=0, depth=2,
-                 epoch_ms=None):
+                 epoch_ms=None, split=False):
         import torch
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
@@ -80,6 +98,7 @@ class Server:
         if epoch_ms is not None and self.depth > 64 - _EPOCH_TOKEN0:
             raise ValueError(f"bounded epochs take one stop token each: depth <= {64 - _EPOCH_TOKEN0}")
         self.epoch_ms = epoch_ms
+        self.split = bool(split) and self.depth > 1
         self._torch = torch
 
     def run(self, workloads, realtime=True, on_done=None):
@@ -102,6 +121,7 @@ class Server:
         bounded = self.epoch_ms is not None
         used = 0
         epochs = 0
+        depths = []
         self.stopped = 0
         self.max_active = 0
         self.max_used = 0
@@ -118,6 +138,12 @@ class Server:
                 pending.popleft()
                 a = _Active()
                 a.wl, a.arrival, a.admitted, a.bytes, a.index = wl, arrival, now, need, i
+                a.tier = 0
+                if self.split:
+                    d = line_depth(wl)
+                    depths.append(d)
+                    below = sum(1 for x in depths if x < d)
+                    a.tier = min(self.depth - 1, below * self.depth // len(depths))
                 a.grid = colt.Grid(wl["grid"])
                 a.job = colt.Job(a.grid, wl["source"], wl["params"], precision=self.precision,
                                  record=self.record)
@@ -132,9 +158,25 @@ class Server:
             # status waits for its launches)
             ready = [a for a in active if not (bounded and id(a) in busy)
                      and a.job.status()[0] < a.job.status()[1]]
+            slot = None
             if ready and len(inflight) < self.depth:
+                taken = {x[2] for x in inflight}
+                for k in range(self.depth):
+                    if k in taken:
+                        continue
+                    if self.split:
+                        cand = []
+                        for tier in range(k, -1, -1):
+                            cand = [a for a in ready if a.tier == tier]
+                            if cand:
+                                break
+                        if not cand:
+                            continue
+                        ready = cand
+                    slot = k
+                    break
+            if slot is not None:
                 quota = max(self.min_quota, self.epoch_photons // len(ready))
-                slot = next(k for k in range(self.depth) if k not in {x[2] for x in inflight})
                 st = streams[slot]
                 st.wait_stream(torch.cuda.current_stream())     # the jobs' uploads
                 token = 0

@@ -18,14 +18,17 @@ def small_stream(n=6, seed=3):
     return jobs
 
 
-@pytest.mark.parametrize("prec", [colt.FP64, colt.FP32_BULK])
-def test_each_job_same_alone_and_in_the_mix(prec):
+@pytest.mark.parametrize("prec,split", [(colt.FP64, False), (colt.FP32_BULK, False),
+                                        (colt.FP64, True)])
+def test_each_job_same_alone_and_in_the_mix(prec, split):
     """Every job's records are the same bit for bit when served in a mix of
-    epochs (the multi-job kernel, slices of uneven jobs) as when run alone (in
-    FP32-bulk, the one-job kernel compiled for its grid kind)."""
+    epochs (the multi-job kernel, slices of uneven jobs, with or without the
+    long-history jobs kept apart) as when run alone (in FP32-bulk, the one-job
+    kernel compiled for its grid kind)."""
     jobs = small_stream()
-    say(f"[gpu] serving mix of {len(jobs)} jobs, precision {prec}")
-    srv = serving.Server(epoch_photons=2048, min_quota=256, precision=prec, record=True)
+    say(f"[gpu] serving mix of {len(jobs)} jobs, precision {prec}, split {split}")
+    srv = serving.Server(epoch_photons=2048, min_quota=256, precision=prec, record=True,
+                         split=split)
     mixed = srv.run(jobs, realtime=False)
     assert srv.max_active == len(jobs) and srv.epochs > 1
     for wl, m in zip(jobs, mixed):

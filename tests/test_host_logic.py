@@ -40,3 +40,15 @@ def test_summary_percentiles_and_rate():
     assert abs(s["p50_ms"] - 1e3 * np.percentile(lat, 50)) < 1e-9
     assert abs(s["p99_ms"] - 1e3 * np.percentile(lat, 99)) < 1e-9
     assert s["p99_ms"] > s["p50_ms"] and s["scatterings_per_s"] == 500.0
+
+
+def test_line_depth_ranks_jobs_by_their_optical_depth():
+    """The split server's ranking proxy is proportional to the line-centre
+    optical depth tau0 of a uniform sphere, whatever the grid resolution, and
+    falls as 1/sqrt(T) at fixed column density."""
+    r = [serving.line_depth(inputs.static_sphere(n=n, tau0=t, n_photons=10)) / t
+         for n, t in ((16, 1e4), (32, 1e6), (48, 3e7), (16, 1e8))]
+    assert np.allclose(r, r[0], rtol=1e-12)
+    a = inputs.static_sphere(n=16, tau0=1e6, n_photons=10)
+    b = {"grid": dict(a["grid"], T=4.0 * np.asarray(a["grid"]["T"]))}
+    assert np.isclose(serving.line_depth(b), 0.5 * serving.line_depth(a), rtol=1e-12)
