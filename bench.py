@@ -114,10 +114,10 @@ def cpu_baseline(n_photons_full, budget_s=15.0):
 def serve_section(n_jobs, scaled=False):
     """The serving stream: n_jobs uniform or Hubble-expanding spheres (grid
     32^3-128^3, tau0 log-uniform in 1e4-1e8, 1e4-1e6 photons log-uniform,
-    global core-skipping, recoil), FP32-bulk.  Capacity with every job arrived
-    at once (equal photon slices per epoch); then Poisson arrivals at 0.8 of
-    that capacity with p50/p99 latency (arrival to tallies on the host), the
-    long-history jobs in epochs of their own; against one job at a time in
+    global core-skipping, recoil), FP32-bulk, the long-history jobs in epochs of
+    their own.  Capacity with every job arrived at once; then Poisson arrivals
+    at 0.8 of that capacity with p50/p99 latency (arrival to tallies on the
+    host); against one job at a time in
     plain FP64, timed on a sample of jobs spread over the stream's range of
     scatterings per job (it would take over an hour for all 512).  scaled:
     the smaller stream of 32^3-64^3 grids, tau0 1e4-1e5, 1e4-5e4 photons."""
@@ -147,10 +147,7 @@ def serve_section(n_jobs, scaled=False):
     for wl in stream:
         t += rng.exponential(1.0 / rate)
         wl["arrival"] = t
-    # the arrivals are served with the long-history jobs kept apart (split):
-    # measured faster than equal slices in p50, p99 and throughput under this
-    # load, while equal slices have the larger capacity when every job has arrived
-    srv = serving.Server(epoch_photons=epoch, min_quota=quota, split=True)
+    srv = serving.Server(epoch_photons=epoch, min_quota=quota)
     out2 = srv.run(stream, realtime=True)
     poisson = serving.summarize(out2, srv.makespan)
     print(f"# serving: Poisson p50/p99 {poisson['p50_ms']:.0f}/{poisson['p99_ms']:.0f} ms",
@@ -170,9 +167,9 @@ def serve_section(n_jobs, scaled=False):
     serial = time.perf_counter() - t0
     serial_rate = scat / serial
     return {"config": dict(cfg, jobs=n_jobs, precision="FP32-bulk", epoch_photons=epoch,
-                           scaled=scaled),
+                           scaled=scaled, split=True),
             "batched": batched,
-            "poisson": dict(poisson, rate_jobs_per_s=rate, offered_load=0.8, split=True,
+            "poisson": dict(poisson, rate_jobs_per_s=rate, offered_load=0.8,
                             epochs=srv.epochs),
             "serial_fp64": {"scatterings_per_s": serial_rate, "sample_jobs": len(picks),
                             "sample_scatterings": scat, "sample_s": serial,

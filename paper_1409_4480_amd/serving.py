@@ -4,13 +4,15 @@ Jobs (workload dictionaries from ``inputs``, each with an arrival time in
 seconds) are admitted in arrival order while their device footprint fits the
 memory budget; every admitted job keeps its grid and tallies resident.  The
 server then runs epochs: one persistent transport launch over the next slice
-of photons of every active job (``colt_transport`` with ``photons_per_job``),
-so jobs that arrive while others are running join at the next epoch and share
+of photons of active jobs (``colt_transport`` with ``photons_per_job``), so
+jobs that arrive while others are running join at the next epoch and share
 the device with them.  Up to ``depth`` epochs are in flight on separate
 streams, so an epoch's last long-lived photons share the device with the next
 epoch instead of holding it alone (a job's slices cover disjoint photon ids and
-its tallies are atomic, so overlapping epochs are safe).  A job's latency runs
-from its arrival to its tallies being on the host.
+its tallies are atomic, so overlapping epochs are safe).  An epoch ends with
+its longest photon histories, so jobs whose histories are long (high optical
+depth) run in epochs of their own, apart from the others.  A job's latency
+runs from its arrival to its tallies being on the host.
 
 Scheduling only: all transport work happens in the HIP library.
 """
@@ -71,18 +73,20 @@ class Server:
                     in a later epoch, so the jobs whose photons are done leave
                     without waiting for the longest histories of the others
                     (a job is then in one epoch at a time)
-    split           keep jobs with long photon histories out of the epochs of
-                    jobs with short ones: each job falls in one of `depth`
+    split           (default) keep jobs with long photon histories out of the
+                    epochs of jobs with short ones (False: every epoch takes
+                    every active job): each job falls in one of `depth`
                     tiers by the rank of its line_depth among the jobs admitted
                     so far, and stream slot k runs epochs of tier k (or, when
-                    it has nothing ready, of the nearest lighter tier), so a
-                    short job's epoch does not last as long as the longest
-                    histories of the mix
+                    it has nothing ready, of the nearest lighter tier; when no
+                    job of tier k or lighter is active, of the nearest heavier
+                    one), so a short job's epoch does not last as long as the
+                    longest histories of the mix
     """
 
     def __init__(self, budget_bytes=None, epoch_photons=1 << 20, min_quota=8192,
                  precision=colt.FP32_BULK, record=False, block=0, blocks_per_cu=0, depth=2,
-                 epoch_ms=None, split=False):
+                 epoch_ms=None, split=True):
         import torch
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
@@ -170,6 +174,11 @@ class Server:
                             cand = [a for a in ready if a.tier == tier]
                             if cand:
                                 break
+                        if not cand and not any(a.tier <= k for a in active):
+                            for tier in range(k + 1, self.depth):
+                                cand = [a for a in ready if a.tier == tier]
+                                if cand:
+                                    break
                         if not cand:
                             continue
                         ready = cand
