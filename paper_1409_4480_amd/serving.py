@@ -82,11 +82,17 @@ class Server:
                     job of tier k or lighter is active, of the nearest heavier
                     one), so a short job's epoch does not last as long as the
                     longest histories of the mix
+    tail_live       the transport's tail rule for every epoch (0: off): once
+                    an epoch's photons are all handed out, a wave holding fewer
+                    than this many live photons suspends them, and they resume
+                    in the job's next epoch beside fresh work, so an epoch does
+                    not wait for its longest histories (a job is then in one
+                    epoch at a time)
     """
 
     def __init__(self, budget_bytes=None, epoch_photons=1 << 20, min_quota=8192,
                  precision=colt.FP32_BULK, record=False, block=0, blocks_per_cu=0, depth=2,
-                 epoch_ms=None, split=True):
+                 epoch_ms=None, split=True, tail_live=16):
         import torch
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
@@ -103,6 +109,9 @@ class Server:
             raise ValueError(f"bounded epochs take one stop token each: depth <= {64 - _EPOCH_TOKEN0}")
         self.epoch_ms = epoch_ms
         self.split = bool(split) and self.depth > 1
+        if not 0 <= int(tail_live) <= 64:
+            raise ValueError("tail_live is a number of lanes, 0..64")
+        self.tail_live = int(tail_live)
         self._torch = torch
 
     def run(self, workloads, realtime=True, on_done=None):
@@ -123,6 +132,7 @@ class Server:
         active = []
         inflight = deque()             # [event, ids of the jobs, stream slot, start, stop asked]
         bounded = self.epoch_ms is not None
+        may_stop = bounded or self.tail_live > 0
         used = 0
         epochs = 0
         depths = []
@@ -160,7 +170,7 @@ class Server:
                 busy |= x[1]
             # a job whose launches may have stopped is asked only when idle (its
             # status waits for its launches)
-            ready = [a for a in active if not (bounded and id(a) in busy)
+            ready = [a for a in active if not (may_stop and id(a) in busy)
                      and a.job.status()[0] < a.job.status()[1]]
             slot = None
             if ready and len(inflight) < self.depth:
@@ -194,7 +204,8 @@ class Server:
                     colt.stop_set(token, False)
                 colt.transport([a.job for a in ready], photons_per_job=quota, block=self.block,
                                blocks_per_cu=self.blocks_per_cu,
-                               stream=ctypes.c_void_p(st.cuda_stream), stop_token=token)
+                               stream=ctypes.c_void_p(st.cuda_stream), stop_token=token,
+                               tail_live=self.tail_live)
                 ev = torch.cuda.Event()
                 ev.record(st)
                 inflight.append([ev, {id(a) for a in ready}, slot, time.perf_counter(), False])

@@ -41,6 +41,30 @@ def test_each_job_same_alone_and_in_the_mix(prec, split):
 
 
 @pytest.mark.parametrize("prec", [colt.FP64, colt.FP32_BULK])
+def test_tail_rule_epochs_give_each_job_its_own_results(prec):
+    """Epochs under the tail rule (every wave with fewer than 64 live photons
+    suspends them once the epoch's queue is drained; the epochs are large
+    enough for the rule to apply: every job has more than the 16384 photons a
+    launch needs for it) resume the suspended photons in later epochs, and
+    each job still gets the records it gets alone."""
+    jobs = inputs.job_stream(n_jobs=3, seed=12, n_range=(16, 32), tau_range=(1e4, 1e5),
+                             ph_range=(17000, 30000))
+    say(f"[gpu] serving with the tail rule, {len(jobs)} jobs, precision {prec}")
+    srv = serving.Server(epoch_photons=1 << 16, min_quota=8192, precision=prec, record=True,
+                         tail_live=64)
+    mixed = srv.run(jobs, realtime=False)
+    say(f"    {srv.epochs} epochs")
+    assert srv.epochs > len(jobs)
+    for wl, m in zip(jobs, mixed):
+        alone = colt.run(wl, precision=prec, record=True)
+        for k in ("x", "nscat", "status", "pos"):
+            assert np.array_equal(alone["records"][k], m["records"][k]), (wl["name"], k)
+        assert np.array_equal(alone["spectrum"], m["spectrum"])
+        for k in ("emitted", "escaped", "scat_hi", "upar_tries", "crossings"):
+            assert alone["counters"][k] == m["counters"][k]
+
+
+@pytest.mark.parametrize("prec", [colt.FP64, colt.FP32_BULK])
 def test_bounded_epochs_stop_and_resume_bit_for_bit(prec):
     """With a time bound of zero every epoch is asked to stop as soon as the
     host sees it running: photons in flight are suspended and resumed in later
