@@ -65,7 +65,7 @@ class Server:
     """Admits jobs by HBM footprint and runs them in shared epochs.
 
     budget_bytes    device memory the server may hold (None: 90 % of free HBM)
-    epoch_photons   photons per epoch, split evenly over the active jobs
+    epoch_photons   photons per epoch, split evenly over the epoch's jobs
     min_quota       smallest per-job slice of an epoch
     depth           epochs in flight at once, each on a stream of its own
     epoch_ms        None, or a time after which a running epoch is asked to stop:
