@@ -167,7 +167,7 @@ def serve_section(n_jobs, scaled=False):
     serial = time.perf_counter() - t0
     serial_rate = scat / serial
     return {"config": dict(cfg, jobs=n_jobs, precision="FP32-bulk", epoch_photons=epoch,
-                           scaled=scaled, split=True),
+                           scaled=scaled, split=srv.split, tail_live=srv.tail_live),
             "batched": batched,
             "poisson": dict(poisson, rate_jobs_per_s=rate, offered_load=0.8,
                             epochs=srv.epochs),
