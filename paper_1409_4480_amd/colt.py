@@ -92,7 +92,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ColtError(f"HIP library {LIB_PATH} not built; run __graft_entry__.build()")
+            raise ColtError(f"HIP library {LIB_PATH} not built; run "
+                            "python -m paper_1409_4480_amd.build")
         # torch's HIP runtime must be the process's runtime: load it first so the
         # library's libamdhip64 dependency resolves to the copy torch uses.
         import torch  # noqa: F401
