@@ -114,6 +114,34 @@ class Server:
         self.tail_live = int(tail_live)
         self._torch = torch
 
+    def _tier_of(self, d, depths):
+        """The tier of a job whose line_depth is d among the line_depths of
+        the jobs admitted so far (d included)."""
+        below = sum(1 for x in depths if x < d)
+        return min(self.depth - 1, below * self.depth // len(depths))
+
+    def _next_epoch(self, ready, active, taken):
+        """The stream slot and the jobs of the next epoch, or (None, []): the
+        first free slot that has jobs to run.  Without the split that is every
+        ready job; with it, slot k takes tier k, else the nearest lighter tier
+        with ready jobs, else (only when no job of tier k or lighter is active
+        at all) the nearest heavier one."""
+        for k in range(self.depth):
+            if k in taken:
+                continue
+            if not self.split:
+                return k, ready
+            for tier in range(k, -1, -1):
+                cand = [a for a in ready if a.tier == tier]
+                if cand:
+                    return k, cand
+            if not any(a.tier <= k for a in active):
+                for tier in range(k + 1, self.depth):
+                    cand = [a for a in ready if a.tier == tier]
+                    if cand:
+                        return k, cand
+        return None, []
+
     def run(self, workloads, realtime=True, on_done=None):
         """Serves the jobs; returns one result dict per job, in input order.
 
@@ -154,10 +182,8 @@ class Server:
                 a.wl, a.arrival, a.admitted, a.bytes, a.index = wl, arrival, now, need, i
                 a.tier = 0
                 if self.split:
-                    d = line_depth(wl)
-                    depths.append(d)
-                    below = sum(1 for x in depths if x < d)
-                    a.tier = min(self.depth - 1, below * self.depth // len(depths))
+                    depths.append(line_depth(wl))
+                    a.tier = self._tier_of(depths[-1], depths)
                 a.grid = colt.Grid(wl["grid"])
                 a.job = colt.Job(a.grid, wl["source"], wl["params"], precision=self.precision,
                                  record=self.record)
@@ -174,26 +200,7 @@ class Server:
                      and a.job.status()[0] < a.job.status()[1]]
             slot = None
             if ready and len(inflight) < self.depth:
-                taken = {x[2] for x in inflight}
-                for k in range(self.depth):
-                    if k in taken:
-                        continue
-                    if self.split:
-                        cand = []
-                        for tier in range(k, -1, -1):
-                            cand = [a for a in ready if a.tier == tier]
-                            if cand:
-                                break
-                        if not cand and not any(a.tier <= k for a in active):
-                            for tier in range(k + 1, self.depth):
-                                cand = [a for a in ready if a.tier == tier]
-                                if cand:
-                                    break
-                        if not cand:
-                            continue
-                        ready = cand
-                    slot = k
-                    break
+                slot, ready = self._next_epoch(ready, active, {x[2] for x in inflight})
             if slot is not None:
                 quota = max(self.min_quota, self.epoch_photons // len(ready))
                 st = streams[slot]

@@ -52,3 +52,41 @@ def test_line_depth_ranks_jobs_by_their_optical_depth():
     a = inputs.static_sphere(n=16, tau0=1e6, n_photons=10)
     b = {"grid": dict(a["grid"], T=4.0 * np.asarray(a["grid"]["T"]))}
     assert np.isclose(serving.line_depth(b), 0.5 * serving.line_depth(a), rtol=1e-12)
+
+
+class _Stub:
+    def __init__(self, tier):
+        self.tier = tier
+
+
+def test_split_epochs_keep_long_history_jobs_apart():
+    """Slot 0 runs the short-history tier only while any short job is
+    active; the long-history slot runs its own tier, else short jobs; a taken
+    slot is skipped; without the split an epoch takes every ready job."""
+    srv = serving.Server(budget_bytes=1 << 30, depth=2)
+    s0, s1, l0, l1 = _Stub(0), _Stub(0), _Stub(1), _Stub(1)
+    act = [s0, s1, l0, l1]
+    assert srv._next_epoch([s0, l0, l1], act, set()) == (0, [s0])
+    assert srv._next_epoch([s0, l0, l1], act, {0}) == (1, [l0, l1])
+    assert srv._next_epoch([s0, s1], act, {0}) == (1, [s0, s1])
+    # short jobs active but none ready: slot 0 waits, the long jobs take slot 1
+    assert srv._next_epoch([l0], act, set()) == (1, [l0])
+    assert srv._next_epoch([l0], act, {1}) == (None, [])
+    # no short job active at all: slot 0 takes the long-history jobs too
+    assert srv._next_epoch([l0, l1], [l0, l1], {1}) == (0, [l0, l1])
+    fair = serving.Server(budget_bytes=1 << 30, depth=2, split=False)
+    assert fair._next_epoch([s0, l0], act, {0}) == (1, [s0, l0])
+
+
+def test_tiers_follow_the_rank_among_admitted_jobs():
+    srv = serving.Server(budget_bytes=1 << 30, depth=2)
+    depths = []
+    tiers = []
+    for d in (5.0, 1.0, 9.0, 3.0, 7.0, 2.0):
+        depths.append(d)
+        tiers.append(srv._tier_of(d, depths))
+    # the first job is alone (tier 0); later ones are heavy from the median up
+    assert tiers == [0, 0, 1, 0, 1, 0]
+    three = serving.Server(budget_bytes=1 << 30, depth=3)
+    ds = [float(i) for i in range(9)]
+    assert [three._tier_of(d, ds) for d in ds] == [0, 0, 0, 1, 1, 1, 2, 2, 2]
