@@ -53,11 +53,12 @@ class _Active:
 def line_depth(wl):
     """A proxy, for ranking jobs only, of how long a job's photon histories
     run: the largest n_HI / sqrt(T) of its cells (the line-centre opacity
-    scales so) times half the domain's widest extent."""
+    scales so) times the distance from the domain's centre to its nearest
+    face (half its narrowest extent)."""
     g = wl["grid"]
     n = np.asarray(g["n_HI"], float)
     t = np.asarray(g["T"], float)
-    width = float(np.max(np.asarray(g["box_max"], float) - np.asarray(g["box_min"], float)))
+    width = float(np.min(np.asarray(g["box_max"], float) - np.asarray(g["box_min"], float)))
     return float(np.max(n / np.sqrt(t))) * 0.5 * width
 
 

@@ -44,10 +44,12 @@ def test_summary_percentiles_and_rate():
 
 def test_line_depth_ranks_jobs_by_their_optical_depth():
     """The split server's ranking proxy is proportional to the line-centre
-    optical depth tau0 of a uniform sphere, whatever the grid resolution, and
-    falls as 1/sqrt(T) at fixed column density."""
+    optical depth tau0 of a uniform sphere, whatever the grid resolution, with
+    the same constant for a slab (whose tau0 is across its thin direction),
+    and falls as 1/sqrt(T) at fixed column density."""
     r = [serving.line_depth(inputs.static_sphere(n=n, tau0=t, n_photons=10)) / t
          for n, t in ((16, 1e4), (32, 1e6), (48, 3e7), (16, 1e8))]
+    r += [serving.line_depth(inputs.slab(tau0=t, n_photons=10)) / t for t in (1e5, 1e7)]
     assert np.allclose(r, r[0], rtol=1e-12)
     a = inputs.static_sphere(n=16, tau0=1e6, n_photons=10)
     b = {"grid": dict(a["grid"], T=4.0 * np.asarray(a["grid"]["T"]))}
