@@ -170,7 +170,11 @@ def serve_section(n_jobs, scaled=False):
                            scaled=scaled, split=srv.split, tail_live=srv.tail_live),
             "batched": batched,
             "poisson": dict(poisson, rate_jobs_per_s=rate, offered_load=0.8,
-                            epochs=srv.epochs),
+                            offered_scatterings_per_s=rate * poisson["scatterings"] / n_jobs,
+                            epochs=srv.epochs,
+                            note="offered: the arrival rate times the mean scatterings per "
+                                 "job; a run that sustains less than it was offered fell "
+                                 "behind its arrivals and its latencies include the backlog"),
             "serial_fp64": {"scatterings_per_s": serial_rate, "sample_jobs": len(picks),
                             "sample_scatterings": scat, "sample_s": serial,
                             "sample": "jobs spread over the stream's scatterings per job "
