@@ -107,7 +107,8 @@ class Server:
         self.blocks_per_cu = blocks_per_cu
         self.depth = max(1, int(depth))
         if epoch_ms is not None and self.depth > 64 - _EPOCH_TOKEN0:
-            raise ValueError(f"bounded epochs take one stop token each: depth <= {64 - _EPOCH_TOKEN0}")
+            raise ValueError("bounded epochs take one stop token each: "
+                             f"depth <= {64 - _EPOCH_TOKEN0}")
         self.epoch_ms = epoch_ms
         self.split = bool(split) and self.depth > 1
         if not 0 <= int(tail_live) <= 64:
@@ -147,7 +148,10 @@ class Server:
         """Serves the jobs; returns one result dict per job, in input order.
 
         With realtime=False every job is taken as arrived at time 0.  on_done,
-        if given, is called as on_done(index, result) as each job finishes.
+        if given, is called as on_done(index, result) as each job finishes.  If
+        a launch or on_done raises, the epochs in flight are waited for and
+        every job and grid the server holds is released before the error
+        propagates.
         """
         order = sorted(range(len(workloads)),
                        key=lambda i: workloads[i].get("arrival", 0.0) if realtime else 0.0)
@@ -169,100 +173,114 @@ class Server:
         self.max_active = 0
         self.max_used = 0
         t0 = time.perf_counter()
-        while pending or active:
-            now = time.perf_counter() - t0
-            while pending:
-                i = pending[0]
-                wl = workloads[i]
-                arrival = wl.get("arrival", 0.0) if realtime else 0.0
-                need = footprint(wl, self.record, self.precision)
-                if arrival > now or used + need > self.budget:
-                    break
-                pending.popleft()
-                a = _Active()
-                a.wl, a.arrival, a.admitted, a.bytes, a.index = wl, arrival, now, need, i
-                a.tier = 0
-                if self.split:
-                    depths.append(line_depth(wl))
-                    a.tier = self._tier_of(depths[-1], depths)
-                a.grid = colt.Grid(wl["grid"])
-                a.job = colt.Job(a.grid, wl["source"], wl["params"], precision=self.precision,
-                                 record=self.record)
-                used += need
-                self.max_used = max(self.max_used, used)
-                active.append(a)
-            self.max_active = max(self.max_active, len(active))
-            busy = set()
-            for x in inflight:
-                busy |= x[1]
-            # a job whose launches may have stopped is asked only when idle (its
-            # status waits for its launches)
-            ready = [a for a in active if not (may_stop and id(a) in busy)
-                     and a.job.status()[0] < a.job.status()[1]]
-            slot = None
-            if ready and len(inflight) < self.depth:
-                slot, ready = self._next_epoch(ready, active, {x[2] for x in inflight})
-            if slot is not None:
-                quota = max(self.min_quota, self.epoch_photons // len(ready))
-                st = streams[slot]
-                st.wait_stream(torch.cuda.current_stream())     # the jobs' uploads
-                token = 0
-                if bounded:
-                    token = _EPOCH_TOKEN0 + slot
-                    colt.stop_set(token, False)
-                colt.transport([a.job for a in ready], photons_per_job=quota, block=self.block,
-                               blocks_per_cu=self.blocks_per_cu,
-                               stream=ctypes.c_void_p(st.cuda_stream), stop_token=token,
-                               tail_live=self.tail_live)
-                ev = torch.cuda.Event()
-                ev.record(st)
-                inflight.append([ev, {id(a) for a in ready}, slot, time.perf_counter(), False])
-                epochs += 1
-                continue
-            if inflight:
-                # wait for an epoch to end, or for the next arrival to admit it;
-                # a bounded epoch past its time is asked to stop
-                while not any(x[0].query() for x in inflight):
-                    if bounded:
-                        tnow = time.perf_counter()
-                        for x in inflight:
-                            if not x[4] and (tnow - x[3]) * 1e3 > self.epoch_ms:
-                                colt.stop_set(_EPOCH_TOKEN0 + x[2], True)
-                                x[4] = True
-                                self.stopped += 1
-                    if realtime and pending and \
-                            time.perf_counter() - t0 >= workloads[pending[0]].get("arrival", 0.0):
+        try:
+            while pending or active:
+                now = time.perf_counter() - t0
+                while pending:
+                    i = pending[0]
+                    wl = workloads[i]
+                    arrival = wl.get("arrival", 0.0) if realtime else 0.0
+                    need = footprint(wl, self.record, self.precision)
+                    if arrival > now or used + need > self.budget:
                         break
-                    time.sleep(2e-4)
-                inflight = deque(x for x in inflight if not x[0].query())
-            elif not active:
-                nxt = workloads[pending[0]].get("arrival", 0.0)
-                time.sleep(max(0.0, min(nxt - (time.perf_counter() - t0), 0.05)))
-                continue
-            busy = set()
+                    pending.popleft()
+                    a = _Active()
+                    a.wl, a.arrival, a.admitted, a.bytes, a.index = wl, arrival, now, need, i
+                    a.tier = 0
+                    if self.split:
+                        depths.append(line_depth(wl))
+                        a.tier = self._tier_of(depths[-1], depths)
+                    a.grid = colt.Grid(wl["grid"])
+                    try:
+                        a.job = colt.Job(a.grid, wl["source"], wl["params"],
+                                         precision=self.precision, record=self.record)
+                    except BaseException:
+                        a.grid.release()
+                        raise
+                    used += need
+                    self.max_used = max(self.max_used, used)
+                    active.append(a)
+                self.max_active = max(self.max_active, len(active))
+                busy = set()
+                for x in inflight:
+                    busy |= x[1]
+                # a job whose launches may have stopped is asked only when idle (its
+                # status waits for its launches)
+                ready = [a for a in active if not (may_stop and id(a) in busy)
+                         and a.job.status()[0] < a.job.status()[1]]
+                slot = None
+                if ready and len(inflight) < self.depth:
+                    slot, ready = self._next_epoch(ready, active, {x[2] for x in inflight})
+                if slot is not None:
+                    quota = max(self.min_quota, self.epoch_photons // len(ready))
+                    st = streams[slot]
+                    st.wait_stream(torch.cuda.current_stream())     # the jobs' uploads
+                    token = 0
+                    if bounded:
+                        token = _EPOCH_TOKEN0 + slot
+                        colt.stop_set(token, False)
+                    colt.transport([a.job for a in ready], photons_per_job=quota, block=self.block,
+                                   blocks_per_cu=self.blocks_per_cu,
+                                   stream=ctypes.c_void_p(st.cuda_stream), stop_token=token,
+                                   tail_live=self.tail_live)
+                    ev = torch.cuda.Event()
+                    ev.record(st)
+                    inflight.append([ev, {id(a) for a in ready}, slot, time.perf_counter(), False])
+                    epochs += 1
+                    continue
+                if inflight:
+                    # wait for an epoch to end, or for the next arrival to admit it;
+                    # a bounded epoch past its time is asked to stop
+                    while not any(x[0].query() for x in inflight):
+                        if bounded:
+                            tnow = time.perf_counter()
+                            for x in inflight:
+                                if not x[4] and (tnow - x[3]) * 1e3 > self.epoch_ms:
+                                    colt.stop_set(_EPOCH_TOKEN0 + x[2], True)
+                                    x[4] = True
+                                    self.stopped += 1
+                        if realtime and pending and time.perf_counter() - t0 >= \
+                                workloads[pending[0]].get("arrival", 0.0):
+                            break
+                        time.sleep(2e-4)
+                    inflight = deque(x for x in inflight if not x[0].query())
+                elif not active:
+                    nxt = workloads[pending[0]].get("arrival", 0.0)
+                    time.sleep(max(0.0, min(nxt - (time.perf_counter() - t0), 0.05)))
+                    continue
+                busy = set()
+                for x in inflight:
+                    busy |= x[1]
+                still = []
+                for a in active:
+                    if id(a) in busy:
+                        still.append(a)
+                        continue
+                    launched, total = a.job.status()
+                    if launched < total:
+                        still.append(a)
+                        continue
+                    out = a.job.tally(wait=True)
+                    done = time.perf_counter() - t0
+                    out["latency_s"] = done - a.arrival
+                    out["queue_s"] = a.admitted - a.arrival
+                    out["finished_s"] = done
+                    results[a.index] = out
+                    if on_done is not None:
+                        on_done(a.index, out)
+                    a.job.release()
+                    a.grid.release()
+                    used -= a.bytes
+                active = still
+        except BaseException:
+            # wait for the epochs in flight, then give back every job and grid the
+            # server holds, before the error goes on to the caller
             for x in inflight:
-                busy |= x[1]
-            still = []
+                x[0].synchronize()
             for a in active:
-                if id(a) in busy:
-                    still.append(a)
-                    continue
-                launched, total = a.job.status()
-                if launched < total:
-                    still.append(a)
-                    continue
-                out = a.job.tally(wait=True)
-                done = time.perf_counter() - t0
-                out["latency_s"] = done - a.arrival
-                out["queue_s"] = a.admitted - a.arrival
-                out["finished_s"] = done
-                results[a.index] = out
-                if on_done is not None:
-                    on_done(a.index, out)
                 a.job.release()
                 a.grid.release()
-                used -= a.bytes
-            active = still
+            raise
         self.epochs = epochs
         self.makespan = time.perf_counter() - t0
         return results

@@ -47,6 +47,11 @@ class _Event:
             self.launch.finish()
         return self.polls >= 3
 
+    def synchronize(self):
+        self.polls = max(self.polls, 3)
+        if self.launch is not None:
+            self.launch.finish()
+
 
 class _Cuda:
     Stream = _Stream
@@ -94,6 +99,7 @@ class _Lib:
     """The library calls the server makes, recording every launch."""
 
     def __init__(self):
+        self.fail_at = None
         self.launches = []
         self.jobs = []
         self.tier_of = {}
@@ -102,6 +108,8 @@ class _Lib:
 
     def transport(self, jobs, photons_per_job=0, stream=None, stop_token=0, tail_live=0,
                   **kw):
+        if self.fail_at is not None and len(self.launches) == self.fail_at:
+            raise serving.colt.ColtError("launch failed")
         may_stop = tail_live > 0 or stop_token != 0
         for j in jobs:
             assert not j.released
@@ -216,3 +224,22 @@ def test_budget_admits_jobs_in_turn(fake):
     fat = dict(jobs[0])
     with pytest.raises(serving.colt.ColtError):
         _server(budget_bytes=sizes[0] // 2).run([fat], realtime=False)
+
+
+@pytest.mark.parametrize("where", ["launch", "on_done"])
+def test_an_error_releases_everything_the_server_holds(fake, where):
+    """A failed launch, or a caller's callback that raises, ends the run with
+    that error after the epochs in flight have finished and every job and grid
+    has been released."""
+    jobs = _stream(n=10, seed=24)
+    srv = _server(epoch_photons=4000, min_quota=100, tail_live=16)
+
+    def done(i, r):
+        if where == "on_done":
+            raise KeyError("caller")
+    if where == "launch":
+        fake.fail_at = 3
+    with pytest.raises(serving.colt.ColtError if where == "launch" else KeyError):
+        srv.run(jobs, realtime=False, on_done=done)
+    assert fake.jobs and all(j.released and j.grid.released for j in fake.jobs)
+    assert all(j.inflight == 0 for j in fake.jobs)
